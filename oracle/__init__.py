@@ -1,0 +1,161 @@
+"""CPU FP64 oracle for chi0(q, omega) -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never calls it and
+shares no code with it.  The arithmetic lives in ``chi0_oracle.c`` (plain C,
+FP64, OpenMP over mesh cells); this module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "chi0_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_chi0.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-shared", "-fPIC",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i, d, ll = ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+        lib.chi0_oracle.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, i, dp,
+                                    ll, ll, i, dp]
+        lib.chi0_oracle.restype = i
+        lib.chi0_oracle_moments.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, dp]
+        lib.chi0_oracle_moments.restype = i
+        lib.chi0_oracle_weights.argtypes = [dp, d, dp]
+        lib.chi0_oracle_weights.restype = None
+        lib.chi0_oracle_dd5.argtypes = [dp, d, dp]
+        lib.chi0_oracle_dd5.restype = None
+        lib.chi0_oracle_carve.argtypes = [dp, dp, i, dp, dp]
+        lib.chi0_oracle_carve.restype = i
+        lib.chi0_oracle_tet_corners.argtypes = [i, i, i, ll, i, ctypes.POINTER(ctypes.c_longlong)]
+        lib.chi0_oracle_tet_corners.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128_as_f64(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.view(np.float64)
+
+
+def chi0_raw(nk, eps_k, c_k, omega, *, eps_kq=None, c_kq=None, shift=(0, 0, 0), mu=0.0,
+             spin_factor=2.0, band_lo=0, band_hi=-1, cma=False, form=0,
+             cells: Optional[Sequence[int]] = None, nthreads: int = 0) -> np.ndarray:
+    """chi0 at one q for all omega: complex array [nw]."""
+    lib = _load()
+    eps_k = _f64(eps_k)
+    nb = eps_k.shape[0]
+    no = 1 if c_k is None else c_k.shape[1]
+    ck = _c128_as_f64(c_k)
+    ekq = _f64(eps_kq)
+    ckq = _c128_as_f64(c_kq)
+    omega = _f64(np.atleast_1d(omega))
+    out = np.zeros((omega.size, 2))
+    c0, c1 = (0, -1) if cells is None else (int(cells[0]), int(cells[1]))
+    rc = lib.chi0_oracle(int(nk[0]), int(nk[1]), int(nk[2]), nb, no, _ptr(eps_k), _ptr(ck), _ptr(ekq),
+                         _ptr(ckq), int(shift[0]), int(shift[1]), int(shift[2]), float(mu),
+                         float(spin_factor), int(band_lo), int(band_hi), int(bool(cma)), int(form),
+                         omega.size, _ptr(omega), c0, c1, int(nthreads), _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle failed with code %d" % rc)
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def chi0(wl, q_index: int, omega=None, cells=None, nthreads: int = 0, form: Optional[int] = None) -> np.ndarray:
+    """chi0 of a synth.Workload at one of its q for the given omegas (default: all)."""
+    q = wl.qs[q_index]
+    om = (np.zeros(1) if wl.static else wl.omega) if omega is None else np.atleast_1d(omega)
+    lo, hi = wl.window()
+    return chi0_raw(wl.nk, wl.eps_k, wl.c_k, om, eps_kq=q.eps_kq, c_kq=q.c_kq,
+                    shift=q.shift if q.shift is not None else (0, 0, 0), mu=wl.mu,
+                    spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi, cma=wl.cma,
+                    form=wl.form if form is None else form, cells=cells, nthreads=nthreads)
+
+
+def moments(wl, q_index: int, pmax: int = 6) -> np.ndarray:
+    """Exact moments mom[p] of the carved integrand: chi0(w) = sum_p mom[p]/w^(p+1) at large w."""
+    lib = _load()
+    q = wl.qs[q_index]
+    lo, hi = wl.window()
+    eps_k = _f64(wl.eps_k)
+    ck = _c128_as_f64(wl.c_k)
+    ekq = _f64(q.eps_kq)
+    ckq = _c128_as_f64(q.c_kq)
+    s = q.shift if q.shift is not None else (0, 0, 0)
+    out = np.zeros(pmax + 1)
+    rc = lib.chi0_oracle_moments(int(wl.nk[0]), int(wl.nk[1]), int(wl.nk[2]), wl.n_bands, wl.n_orb,
+                                 _ptr(eps_k), _ptr(ck), _ptr(ekq), _ptr(ckq), int(s[0]), int(s[1]),
+                                 int(s[2]), float(wl.mu), float(wl.spin_factor), lo, hi,
+                                 int(bool(wl.cma)), pmax, _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle_moments failed with code %d" % rc)
+    return out
+
+
+def weights(D: Sequence[float], w: float) -> np.ndarray:
+    """Corner weights J_j (complex, 4) of 1/(w - D + i0) on a simplex with corner values D."""
+    lib = _load()
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    out = np.zeros(8)
+    lib.chi0_oracle_weights(_ptr(D), float(w), _ptr(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def dd5(nodes: Sequence[float], w: float) -> complex:
+    lib = _load()
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    out = np.zeros(2)
+    lib.chi0_oracle_dd5(_ptr(x), float(w), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def carve(a: Sequence[float], b: Sequence[float], region: int):
+    """Final tetrahedra (barycentric vertices [n][4][4], volume fractions [n]) of a region."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    verts = np.zeros((9, 4, 4))
+    vols = np.zeros(9)
+    n = lib.chi0_oracle_carve(_ptr(a), _ptr(b), int(region), _ptr(verts), _ptr(vols))
+    return verts[:n].copy(), vols[:n].copy()
+
+
+def tet_corners(nk, cell: int, t: int) -> np.ndarray:
+    lib = _load()
+    out = (ctypes.c_longlong * 4)()
+    lib.chi0_oracle_tet_corners(int(nk[0]), int(nk[1]), int(nk[2]), int(cell), int(t), out)
+    return np.array(list(out), dtype=np.int64)
