@@ -1,0 +1,153 @@
+"""Benchmark of the chi0 hot path on one MI355X.
+
+Default workload (the precision-study configuration of the 10-orbital model): the
+seeded two-site tetragonal tight-binding model (10 d-like orbitals, seed 2) on a
+64 x 64 x 8 mesh (196,608 tetrahedra), all 100 band pairs, 64 q at the arc-length
+midpoints of Gamma-X-M-Gamma (explicit k+q eigenpairs), 512 frequencies on [0, 2] eV,
+dynamic chi0 (analytic Re, delta-weight Im), FP64.
+
+One step = one chi0_dynamic call over all 64 q x 512 w: matrix elements (MFMA),
+carving + tetrahedron weights, ordered reduction.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 operations per evaluation, counted from the formulas the tetrahedron kernel evaluates
+# (a logarithm counted as 20 operations): see the roofline section of the design notes.
+FLOPS_FAR = 50       # d = w - c, 1/d, 24-term Horner, accumulate
+FLOPS_NEAR = 200     # 4 logs + leaf values/derivatives + 6 Newton entries with derivatives
+FLOPS_PREP = 350     # sort of 4 nodes + 24 far-series coefficients with derivatives
+FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nq", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    t0 = time.time()
+    wl = synth.make_workload("tetra_dynamic", nq=64, q_subset=list(range(args.nq)), workers=args.workers)
+    log(f"inputs built in {time.time() - t0:.1f}s: mesh {wl.nk}, {len(wl.qs)} q, {len(wl.omega)} w")
+
+    import torch
+    import paper_1407_3444_amd as lib
+    dev = torch.device("cuda:0")
+    eps = torch.from_numpy(wl.eps_k).to(dev)
+    ck = torch.from_numpy(wl.c_k).to(dev)
+    qs = [lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev), c_kq=torch.from_numpy(q.c_kq).to(dev)) for q in wl.qs]
+    om = torch.from_numpy(wl.omega).to(dev)
+    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor)
+    ws = plan.workspace(len(qs), len(wl.omega))
+    out = torch.empty((len(qs), len(wl.omega), 2), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    log(f"resident on device; workspace {ws.numel() / 2**20:.1f} MiB")
+
+    census = plan.census(qs, om, workspace=ws)
+    log("census", census)
+
+    for _ in range(args.warmup):
+        plan.dynamic(qs, om, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    plan.profile(True)
+    plan.read_profile()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        plan.dynamic(qs, om, workspace=ws, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    prof = plan.read_profile()
+    plan.profile(False)
+    log("timed", args.steps, "steps:", f"{ms_total:.1f} ms", prof)
+
+    nw = len(wl.omega)
+    units_per_step = len(qs) * 6 * wl.n_k * 100 * nw
+    ms_step = ms_total / args.steps
+    value = units_per_step * args.steps / (ms_total * 1e-3)
+
+    tet = prof["tetra"]
+    launches_per_step = tet["launches"] / args.steps
+    avg_ms = tet["ms"] / tet["launches"]
+    flops_per_step = (census["far_evals"] * FLOPS_FAR + census["near_evals"] * FLOPS_NEAR
+                      + census["final_tetrahedra"] * FLOPS_PREP)
+    flops_per_launch = flops_per_step / launches_per_step
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "tetra_dynamic_kernel", "avg_launch_ms": round(avg_ms, 3),
+                "launches_per_step": launches_per_step}
+
+    result = {
+        "metric": "chi0 band-pair*tetra*omega updates/s (FP64 GPU)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded tight-binding model, eigenpairs by numpy eigh)",
+        "config": {"workload": "tetragonal two-site 10-orbital TB, 64x64x8 mesh, 64 q x 512 w, dynamic, "
+                               "all 100 band pairs, FP64",
+                   "mesh": list(wl.nk), "n_q": len(qs), "n_omega": nw, "band_pairs": 100,
+                   "tetrahedra": 6 * wl.n_k, "units_per_step": units_per_step,
+                   "active_units_per_step": census["active_units"] * nw,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "census": census,
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        sample_w = [0, 73, 146, 219, 292, 365, 438, 511]
+        t1 = time.time()
+        ref = oracle.chi0(wl, 0, omega=wl.omega[sample_w], nthreads=threads)
+        dt = time.time() - t1
+        units = 6 * wl.n_k * 100 * len(sample_w)
+        got = torch.view_as_complex(out[0]).cpu().numpy()[sample_w]
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        result["cpu_baseline"] = {"value": units / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"q index 0, {len(sample_w)} of 512 w, full 64x64x8 mesh, "
+                                            f"{dt:.1f} s"}
+        result["parity_sample"] = {"max_rel_err_vs_oracle": err, "q": 0, "omega_index": sample_w}
+        log(f"oracle sample {dt:.1f}s, rel err {err:.2e}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

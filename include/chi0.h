@@ -1,0 +1,157 @@
+/*
+ * chi0.h -- C ABI of libchi0, the MI355X (gfx950) library for the bare
+ * (Lindhard) susceptibility chi0(q, omega) by the linear tetrahedron method
+ * with double occupation carving (Heil et al., arXiv:1407.3444, Sec. II).
+ *
+ * What one call computes (Sec. II, Eqs. (1)-(3), carving condition Eq. (4)):
+ *
+ *   chi0(q,w) = g_s/(6 Nk) sum_T sum_{n,m in [band_lo, band_hi)}
+ *               (1/|T|) int_T W_nm(k) [f(e) - f(e')] / (w - (e' - e) + i0) dk
+ *
+ * e = eps_n(k), e' = eps_m(k+q), W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2
+ * (the tight-binding matrix element of the footnote in Sec. III; W = 1 under the
+ * constant matrix-element approximation), all three interpolated linearly on
+ * each of the 6 tetrahedra of every mesh cell.  T = 0, f = step function at mu.
+ * Each tetrahedron is carved twice -- first by e = mu, then by e' = mu -- and
+ * only the final tetrahedra where the product of occupation factors is one
+ * are integrated, analytically.  The result is the retarded response (+i0),
+ * per unit cell, in states per energy unit: Re chi0(q -> 0, 0) = -N(E_F).
+ *
+ * Conventions shared by every entry point
+ *   * Mesh: Gamma-centred N1 x N2 x N3, k = (i1/N1, i2/N2, i3/N3) in fractional
+ *     reciprocal coordinates, flat index k = (i1*N2 + i2)*N3 + i3.  Cell (i1,i2,i3)
+ *     holds the tetrahedra {c, c+e_p0, c+e_p0+e_p1, c+(1,1,1)} for the six axis
+ *     permutations (p0,p1,p2); indices wrap periodically.
+ *   * Band energies: float64, band-major [n_bands][Nk].
+ *   * Eigenvectors: complex128 as interleaved (re, im) float64, [Nk][n_orb][n_bands];
+ *     entry (k, o, n) is orbital o of the eigenvector of band n at k.
+ *   * All array pointers passed to the library are DEVICE pointers (HIP), except
+ *     the chi0_desc and chi0_q structures themselves, which live in host memory.
+ *   * The caller owns all device memory, inputs, workspace and outputs.  The
+ *     library allocates no device memory.  Inputs must stay valid and unmodified
+ *     until the stream work that reads them has completed.
+ *   * Work is enqueued on the HIP stream given to chi0_plan and runs
+ *     asynchronously; outputs are valid once that stream has been synchronised.
+ *   * Errors: every call returns a chi0_status; descriptor and argument checks are
+ *     done on the host before anything is enqueued.  A failure reported by the HIP
+ *     runtime is returned as CHI0_E_DEVICE.  No exception crosses the ABI.
+ *   * A plan is not thread safe: use one plan per host thread.
+ *   * If a final tetrahedron has a whole face on which e' - e equals w (e.g. an
+ *     exactly nested tetrahedron at w = 0), the integral diverges and the output
+ *     for that (q, w) is not finite.
+ */
+#ifndef CHI0_H
+#define CHI0_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum chi0_status {
+    CHI0_OK = 0,
+    CHI0_E_INVALID_ARG = -1,   /* null pointer, bad enum value, negative count */
+    CHI0_E_SHAPE = -2,         /* mesh, band, orbital or window sizes out of range */
+    CHI0_E_NONFINITE = -3,     /* mu, spin factor or an omega is not finite */
+    CHI0_E_WORKSPACE = -5,     /* workspace null or smaller than chi0_workspace_size */
+    CHI0_E_DEVICE = -6,        /* the HIP runtime reported an error */
+    CHI0_E_UNSUPPORTED = -7    /* valid request outside what this build implements */
+} chi0_status;
+
+/* Problem description, copied by chi0_plan. */
+typedef struct chi0_desc {
+    int32_t nk[3];          /* mesh N1, N2, N3 (each >= 1, Nk < 2^31) */
+    int32_t n_bands;        /* bands stored in the energy/eigenvector arrays (1..64) */
+    int32_t n_orb;          /* orbitals per eigenvector (1..64); ignored under cma */
+    int32_t band_lo;        /* first band of the summation window (Sec. III band truncation) */
+    int32_t band_hi;        /* one past the last band; <= 0 means n_bands; window <= 32 bands */
+    int32_t cma;            /* 1: constant matrix elements W = 1 (Sec. III), eigenvectors unused */
+    int32_t form;           /* 0: occupation difference f(e)-f(e') (regions e<mu<e' minus e'<mu<e);
+                               1: the paper's Eq. (1)/(2): region e<mu<e' only, with
+                                  1/(w-D+i0) - 1/(w+D+i0)  (equal to form 0 under time reversal) */
+    int32_t precision;      /* 0: FP64 everywhere (the only value this build accepts) */
+    int32_t reserved[5];    /* must be zero */
+    double mu;              /* Fermi level (energy units of the band arrays) */
+    double spin_factor;     /* g_s, 2 for spin-degenerate bands */
+} chi0_desc;
+
+/* One q.  Either an integer mesh shift (k+q data = mesh data at (i + shift) mod N),
+ * or explicit band data at k+q for every mesh point k. */
+typedef struct chi0_q {
+    int32_t shift[3];       /* used when explicit_kq == 0 */
+    int32_t explicit_kq;    /* 1: eps_kq / c_kq below hold the k+q data */
+    const double *eps_kq;   /* device [n_bands][Nk] float64, energies at k+q */
+    const double *c_kq;     /* device [Nk][n_orb][n_bands] complex128 (re,im), eigenvectors at
+                               k+q; may be NULL under cma */
+} chi0_q;
+
+typedef struct chi0_plan_s *chi0_plan_t;
+
+/* Create a plan.  eps_k: device [n_bands][Nk]; c_k: device [Nk][n_orb][n_bands] complex128,
+ * may be NULL under cma.  hip_stream: a hipStream_t (NULL = default stream).  On success
+ * *out receives the plan, which borrows eps_k and c_k. */
+chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *desc, const double *eps_k,
+                      const double *c_k, void *hip_stream);
+
+/* Device workspace (bytes) needed by chi0_static / chi0_dynamic for nq q-points and nw
+ * frequencies (nw = 1 for the static call). */
+chi0_status chi0_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, size_t *bytes);
+
+/* Static chi0(q, 0) (Sec. III uses Eq. (1) at w = 0, where Im vanishes).
+ * qs: host array of nq chi0_q; chi: device float64 [nq] receives Re chi0(q, 0). */
+chi0_status chi0_static(chi0_plan_t plan, int32_t nq, const chi0_q *qs, void *workspace,
+                        size_t workspace_bytes, double *chi);
+
+/* Dynamic chi0(q, w) on a frequency grid (Sec. IV; Re by the analytic tetrahedron formula,
+ * Im by the tetrahedron delta weights, both exact for the linear interpolant).
+ * omega: device float64 [nw] (any real values, any order); chi: device float64
+ * [nq][nw][2] receives (Re, Im). */
+chi0_status chi0_dynamic(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
+                         const double *omega, void *workspace, size_t workspace_bytes,
+                         double *chi);
+
+/* Matrix elements of one q, the weights the tetrahedron integration interpolates:
+ * W[(n*nbw + m)*Nk + k] = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 (footnote of Sec. III),
+ * n, m relative to band_lo, nbw = band_hi - band_lo.  W: device float64 [nbw][nbw][Nk].
+ * CHI0_E_UNSUPPORTED under cma. */
+chi0_status chi0_matrix_elements(chi0_plan_t plan, const chi0_q *q, double *W);
+
+/* Kernel timing of the plan's launches, measured with HIP events on the plan's stream
+ * while profiling is enabled.  Index 0: matrix-element kernel, 1: tetrahedron kernel,
+ * 2: reduction kernel. */
+typedef struct chi0_profile {
+    double ms[3];           /* summed kernel time in milliseconds */
+    int64_t launches[3];    /* number of launches */
+} chi0_profile;
+
+/* Start (enable = 1) or stop (0) recording events around every launch of this plan. */
+chi0_status chi0_profile_enable(chi0_plan_t plan, int32_t enable);
+
+/* Wait for the recorded events, return the sums since the last read (host struct) and reset. */
+chi0_status chi0_profile_read(chi0_plan_t plan, chi0_profile *out);
+
+/* Work census of chi0_dynamic(plan, nq, qs, nw, omega) without evaluating it (diagnostic):
+ * counts (host uint64 [4]) receives the number of (tetrahedron, band pair, q) units whose
+ * carved region is non-empty, the number of final tetrahedra, and the number of (final
+ * tetrahedron, frequency) evaluations taking the near branch and the far branch of the
+ * weight evaluation.  Uses the same workspace as chi0_dynamic and synchronises the stream. */
+chi0_status chi0_census(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
+                        const double *omega, void *workspace, size_t workspace_bytes,
+                        uint64_t *counts);
+
+/* Release a plan (host memory only).  NULL is accepted. */
+chi0_status chi0_destroy(chi0_plan_t plan);
+
+/* Static description of a status code. */
+const char *chi0_status_string(chi0_status status);
+
+/* Text of the last error recorded on this plan ("" if none). */
+const char *chi0_last_error(chi0_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHI0_H */

@@ -1,0 +1,228 @@
+"""Python binding of libchi0 (MI355X / gfx950 bare-susceptibility library).
+
+Argument marshalling only: every step of the computation (matrix elements,
+carving, tetrahedron weights, reduction) runs in the HIP kernels of
+``libchi0.so``; PyTorch provides device memory and the stream.  There is no
+CPU fallback: if the library is missing, or no GPU is present, the calls raise.
+
+    plan = Chi0Plan(nk, eps_k, c_k, mu=0.0)          # device tensors
+    chi_static = plan.static([Q(shift=(1, 1, 1))])  # float64 [nq]
+    chi = plan.dynamic([Q(eps_kq=e, c_kq=c)], omega) # complex128 [nq, nw]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+__all__ = ["Chi0Plan", "Q", "Chi0Error", "load_library", "LIB_PATH", "EXPORTED_SYMBOLS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
+
+EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
+                    "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
+                    "chi0_destroy", "chi0_status_string", "chi0_last_error"]
+
+STATUS = {0: "CHI0_OK", -1: "CHI0_E_INVALID_ARG", -2: "CHI0_E_SHAPE", -3: "CHI0_E_NONFINITE",
+          -5: "CHI0_E_WORKSPACE", -6: "CHI0_E_DEVICE", -7: "CHI0_E_UNSUPPORTED"}
+
+
+class Chi0Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32 * 3), ("n_bands", ctypes.c_int32), ("n_orb", ctypes.c_int32),
+                ("band_lo", ctypes.c_int32), ("band_hi", ctypes.c_int32), ("cma", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("mu", ctypes.c_double), ("spin_factor", ctypes.c_double)]
+
+
+class _Q(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int32 * 3), ("explicit_kq", ctypes.c_int32),
+                ("eps_kq", ctypes.c_void_p), ("c_kq", ctypes.c_void_p)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_int64 * 3)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libchi0.so and declare its C ABI (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libchi0 not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.chi0_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Desc), vp, vp, vp]
+    lib.chi0_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+    lib.chi0_static.argtypes = [vp, i32, ctypes.POINTER(_Q), vp, sz, vp]
+    lib.chi0_dynamic.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
+    lib.chi0_matrix_elements.argtypes = [vp, ctypes.POINTER(_Q), vp]
+    lib.chi0_profile_enable.argtypes = [vp, i32]
+    lib.chi0_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
+    lib.chi0_census.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+    lib.chi0_destroy.argtypes = [vp]
+    lib.chi0_status_string.argtypes = [i32]
+    lib.chi0_status_string.restype = ctypes.c_char_p
+    lib.chi0_last_error.argtypes = [vp]
+    lib.chi0_last_error.restype = ctypes.c_char_p
+    for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
+                 "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
+                 "chi0_destroy"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Q:
+    """One q: an integer mesh shift, or explicit device band data at k+q."""
+    shift: Sequence[int] = (0, 0, 0)
+    eps_kq: Optional[object] = None    # torch float64 [nb][Nk] on the device
+    c_kq: Optional[object] = None      # torch complex128 [Nk][no][nb] on the device
+
+
+def _dev_ptr(t, dtype_name: str):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libchi0 takes device tensors")
+    if str(t.dtype) != dtype_name:
+        raise ValueError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Chi0Plan:
+    """A chi0 plan over fixed mesh band data (eps_k [nb][Nk], c_k [Nk][no][nb] on the device)."""
+
+    def __init__(self, nk, eps_k, c_k=None, *, mu: float = 0.0, spin_factor: float = 2.0,
+                 band_lo: int = 0, band_hi: int = 0, cma: bool = False, form: int = 0,
+                 precision: int = 0, stream=None):
+        import torch
+        self._lib = load_library()
+        self.nk = tuple(int(v) for v in nk)
+        self.eps_k = eps_k
+        self.c_k = c_k
+        d = _Desc()
+        for i in range(3):
+            d.nk[i] = self.nk[i]
+        d.n_bands = int(eps_k.shape[0])
+        d.n_orb = 1 if c_k is None else int(c_k.shape[1])
+        d.band_lo, d.band_hi = int(band_lo), int(band_hi)
+        d.cma, d.form, d.precision = int(bool(cma)), int(form), int(precision)
+        d.mu, d.spin_factor = float(mu), float(spin_factor)
+        self.nbw = (d.n_bands if band_hi <= 0 else band_hi) - band_lo
+        self.cma = bool(cma)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = ctypes.c_void_p()
+        st = self._lib.chi0_plan(ctypes.byref(handle), ctypes.byref(d), _dev_ptr(eps_k, "torch.float64"),
+                                 _dev_ptr(c_k, "torch.complex128"), ctypes.c_void_p(self._stream.cuda_stream))
+        if st != 0:
+            raise Chi0Error(st, "chi0_plan rejected the description")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.chi0_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != 0:
+            raise Chi0Error(st, f"{what}: {self._lib.chi0_last_error(self._h).decode()}")
+
+    def _qarray(self, qs: Sequence[Q]):
+        arr = (_Q * len(qs))()
+        for i, q in enumerate(qs):
+            if q.eps_kq is not None:
+                arr[i].explicit_kq = 1
+                arr[i].eps_kq = _dev_ptr(q.eps_kq, "torch.float64")
+                arr[i].c_kq = _dev_ptr(q.c_kq, "torch.complex128")
+            else:
+                for a in range(3):
+                    arr[i].shift[a] = int(q.shift[a])
+        return arr
+
+    def workspace_bytes(self, nq: int, nw: int) -> int:
+        n = ctypes.c_size_t()
+        self._check(self._lib.chi0_workspace_size(self._h, nq, nw, ctypes.byref(n)), "chi0_workspace_size")
+        return int(n.value)
+
+    def workspace(self, nq: int, nw: int):
+        import torch
+        return torch.empty(self.workspace_bytes(nq, nw), dtype=torch.uint8, device=self.eps_k.device)
+
+    def static(self, qs: Sequence[Q], workspace=None, out=None):
+        """Re chi0(q, 0) for each q: float64 tensor [nq]."""
+        import torch
+        nq = len(qs)
+        ws = workspace if workspace is not None else self.workspace(nq, 1)
+        chi = out if out is not None else torch.empty(nq, dtype=torch.float64, device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_static(self._h, nq, arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_static")
+        return chi
+
+    def dynamic(self, qs: Sequence[Q], omega, workspace=None, out=None):
+        """chi0(q, w): complex128 tensor [nq, nw] (omega: float64 device tensor [nw])."""
+        import torch
+        nq, nw = len(qs), int(omega.shape[0])
+        ws = workspace if workspace is not None else self.workspace(nq, nw)
+        chi = out if out is not None else torch.empty((nq, nw, 2), dtype=torch.float64, device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_dynamic(self._h, nq, arr, nw, _dev_ptr(omega, "torch.float64"),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_dynamic")
+        return torch.view_as_complex(chi)
+
+    def matrix_elements(self, q: Q, out=None):
+        """W_nm(k) of one q: float64 tensor [nbw, nbw, Nk]."""
+        import torch
+        nkt = self.nk[0] * self.nk[1] * self.nk[2]
+        W = out if out is not None else torch.empty((self.nbw, self.nbw, nkt), dtype=torch.float64,
+                                                    device=self.eps_k.device)
+        arr = self._qarray([q])
+        self._check(self._lib.chi0_matrix_elements(self._h, arr, ctypes.c_void_p(W.data_ptr())),
+                    "chi0_matrix_elements")
+        return W
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every launch of this plan (see read_profile)."""
+        self._check(self._lib.chi0_profile_enable(self._h, int(bool(enable))), "chi0_profile_enable")
+
+    def read_profile(self) -> dict:
+        """Kernel times (ms) and launch counts since the last read: keys contract/tetra/reduce."""
+        prof = _Profile()
+        self._check(self._lib.chi0_profile_read(self._h, ctypes.byref(prof)), "chi0_profile_read")
+        names = ("contract", "tetra", "reduce")
+        return {n: {"ms": prof.ms[i], "launches": int(prof.launches[i])} for i, n in enumerate(names)}
+
+    def census(self, qs: Sequence[Q], omega, workspace=None) -> dict:
+        """Work census of dynamic(qs, omega) (diagnostic; synchronises)."""
+        nq, nw = len(qs), int(omega.shape[0])
+        ws = workspace if workspace is not None else self.workspace(nq, nw)
+        arr = self._qarray(qs)
+        counts = (ctypes.c_uint64 * 4)()
+        st = self._lib.chi0_census(self._h, nq, arr, nw, _dev_ptr(omega, "torch.float64"),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), counts)
+        self._check(st, "chi0_census")
+        return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
+                "near_evals": int(counts[2]), "far_evals": int(counts[3])}

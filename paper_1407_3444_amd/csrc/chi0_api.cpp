@@ -1,0 +1,372 @@
+// chi0_api.cpp -- the C ABI of libchi0: argument checks, workspace layout and the
+// launch sequence per batch of q-points:
+//   K_A  matrix elements W_nm(k) for every q of the batch (skipped under CMA)
+//   K_B  carving + tetrahedron weights -> per-workgroup partial sums
+//   K_R  ordered reduction of the partial sums -> chi0(q, w)
+// Every check is done on the host before anything is enqueued.
+#include "../../include/chi0.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "chi0_internal.h"
+
+using namespace chi0;
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+struct chi0_plan_s {
+    chi0_desc d;
+    MeshDev mesh;
+    hipStream_t stream;
+    std::string err;
+    bool profiling = false;
+    std::vector<TimedLaunch> events;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+chi0_status fail(chi0_plan_t p, chi0_status st, const char *msg)
+{
+    if (p) p->err = msg;
+    return st;
+}
+
+chi0_status device_fail(chi0_plan_t p, hipError_t e, const char *where)
+{
+    if (p) {
+        p->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return CHI0_E_DEVICE;
+}
+
+int64_t n_units(const chi0_plan_s *p)
+{
+    return 6 * p->mesh.nk * (int64_t)p->mesh.nbw * p->mesh.nbw;
+}
+
+// Units per workgroup: about 1024 workgroups per q, at least 4 rounds of 64.
+int64_t units_per_block(const chi0_plan_s *p)
+{
+    const int64_t u = n_units(p);
+    int64_t upb = (u + 1023) / 1024;
+    upb = (upb + kWave - 1) / kWave * kWave;
+    return std::max<int64_t>(upb, 4 * kWave);
+}
+
+int n_blocks(const chi0_plan_s *p)
+{
+    const int64_t upb = units_per_block(p);
+    return (int)((n_units(p) + upb - 1) / upb);
+}
+
+struct Layout {
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, count_off, total;
+    int qbatch;
+};
+
+Layout layout(const chi0_plan_s *p, int nq, int nvals)
+{
+    Layout L;
+    L.qbatch = std::min(nq, kMaxQBatch);
+    L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
+    L.part_bytes_per_q = align_up(sizeof(double) * (size_t)n_blocks(p) * nvals);
+    L.w_off = 0;
+    L.part_off = L.w_bytes_per_q * L.qbatch;
+    L.count_off = L.part_off + L.part_bytes_per_q * L.qbatch;
+    L.total = L.count_off + kAlign;       // census counters
+    return L;
+}
+
+chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
+{
+    if (nq < 1 || !qs) return fail(p, CHI0_E_INVALID_ARG, "nq must be >= 1 and qs non-null");
+    for (int i = 0; i < nq; ++i) {
+        const chi0_q &q = qs[i];
+        if (q.explicit_kq != 0 && q.explicit_kq != 1) return fail(p, CHI0_E_INVALID_ARG, "explicit_kq must be 0 or 1");
+        if (q.explicit_kq) {
+            if (!q.eps_kq) return fail(p, CHI0_E_INVALID_ARG, "explicit q without eps_kq");
+            if (!p->d.cma && !q.c_kq) return fail(p, CHI0_E_INVALID_ARG, "explicit q without c_kq");
+        }
+    }
+    return CHI0_OK;
+}
+
+void fill_batch(const chi0_plan_s *p, const chi0_q *qs, int q0, int nqb, void *ws, const Layout &L, BatchDev &B)
+{
+    std::memset(&B, 0, sizeof B);
+    const int n[3] = {p->mesh.n1, p->mesh.n2, p->mesh.n3};
+    for (int i = 0; i < nqb; ++i) {
+        const chi0_q &q = qs[q0 + i];
+        QDev &d = B.q[i];
+        d.explicit_kq = q.explicit_kq;
+        if (q.explicit_kq) {
+            d.eps_kq = q.eps_kq;
+            d.c_kq = q.c_kq;
+        } else {
+            d.eps_kq = p->mesh.eps_k;
+            d.c_kq = p->mesh.c_k;
+            for (int a = 0; a < 3; ++a) d.shift[a] = ((q.shift[a] % n[a]) + n[a]) % n[a];
+        }
+        d.W = p->d.cma ? nullptr : reinterpret_cast<double *>(static_cast<char *>(ws) + L.w_off + L.w_bytes_per_q * i);
+    }
+}
+
+// Run one launch, bracketed by events when profiling.
+template <class F>
+hipError_t timed(chi0_plan_s *p, int kind, F &&launch)
+{
+    if (!p->profiling) return launch();
+    TimedLaunch t;
+    t.kind = kind;
+    hipError_t e = hipEventCreate(&t.start);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&t.stop)) != hipSuccess) return e;
+    if ((e = hipEventRecord(t.start, p->stream)) != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(t.stop, p->stream)) != hipSuccess) return e;
+    p->events.push_back(t);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *chi0_status_string(chi0_status s)
+{
+    switch (s) {
+    case CHI0_OK: return "ok";
+    case CHI0_E_INVALID_ARG: return "invalid argument";
+    case CHI0_E_SHAPE: return "shape out of range";
+    case CHI0_E_NONFINITE: return "non-finite input";
+    case CHI0_E_WORKSPACE: return "workspace too small";
+    case CHI0_E_DEVICE: return "device error";
+    case CHI0_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *chi0_last_error(chi0_plan_t p) { return p ? p->err.c_str() : ""; }
+
+chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *d, const double *eps_k, const double *c_k, void *stream)
+{
+    if (!out || !d) return CHI0_E_INVALID_ARG;
+    *out = nullptr;
+    for (int i = 0; i < 3; ++i)
+        if (d->nk[i] < 1) return CHI0_E_SHAPE;
+    const int64_t nk = (int64_t)d->nk[0] * d->nk[1] * d->nk[2];
+    if (nk >= (int64_t(1) << 31)) return CHI0_E_SHAPE;
+    if (d->n_bands < 1 || d->n_bands > 64) return CHI0_E_SHAPE;
+    const int hi = d->band_hi <= 0 ? d->n_bands : d->band_hi;
+    if (d->band_lo < 0 || d->band_lo >= hi || hi > d->n_bands) return CHI0_E_SHAPE;
+    if (hi - d->band_lo > 32) return CHI0_E_SHAPE;
+    if (d->cma != 0 && d->cma != 1) return CHI0_E_INVALID_ARG;
+    if (!d->cma && (d->n_orb < 1 || d->n_orb > 64)) return CHI0_E_SHAPE;
+    if (d->form != 0 && d->form != 1) return CHI0_E_INVALID_ARG;
+    for (int i = 0; i < 5; ++i)
+        if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;
+    if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor)) return CHI0_E_NONFINITE;
+    if (d->precision != 0) return CHI0_E_UNSUPPORTED;
+    if (!eps_k) return CHI0_E_INVALID_ARG;
+    if (!d->cma && !c_k) return CHI0_E_INVALID_ARG;
+    // 6 Nk nbw^2 units must fit the 64-bit unit index and the per-q block count an int
+    chi0_plan_s *p = new (std::nothrow) chi0_plan_s();
+    if (!p) return CHI0_E_INVALID_ARG;
+    p->d = *d;
+    p->d.band_hi = hi;
+    MeshDev &M = p->mesh;
+    M.n1 = d->nk[0];
+    M.n2 = d->nk[1];
+    M.n3 = d->nk[2];
+    M.nk = nk;
+    M.nb = d->n_bands;
+    M.no = d->cma ? 1 : d->n_orb;
+    M.lo = d->band_lo;
+    M.nbw = hi - d->band_lo;
+    M.cma = d->cma;
+    M.form = d->form;
+    M.mu = d->mu;
+    M.eps_k = eps_k;
+    M.c_k = c_k;
+    p->stream = static_cast<hipStream_t>(stream);
+    *out = p;
+    return CHI0_OK;
+}
+
+chi0_status chi0_destroy(chi0_plan_t p)
+{
+    if (p) {
+        for (auto &t : p->events) {
+            (void)hipEventDestroy(t.start);
+            (void)hipEventDestroy(t.stop);
+        }
+    }
+    delete p;
+    return CHI0_OK;
+}
+
+chi0_status chi0_profile_enable(chi0_plan_t p, int32_t enable)
+{
+    if (!p || (enable != 0 && enable != 1)) return CHI0_E_INVALID_ARG;
+    p->profiling = enable == 1;
+    return CHI0_OK;
+}
+
+chi0_status chi0_profile_read(chi0_plan_t p, chi0_profile *out)
+{
+    if (!p || !out) return CHI0_E_INVALID_ARG;
+    std::memset(out, 0, sizeof *out);
+    chi0_status st = CHI0_OK;
+    for (auto &t : p->events) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) st = device_fail(p, e, "profile events");
+        out->ms[t.kind] += ms;
+        out->launches[t.kind] += 1;
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    p->events.clear();
+    return st;
+}
+
+chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega, void *ws,
+                        size_t ws_bytes, uint64_t *counts)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (nw < 1 || !omega || !counts) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and counts required");
+    const Layout L = layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch));
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
+    hipError_t e = hipMemsetAsync(dc, 0, 4 * sizeof(unsigned long long), p->stream);
+    if (e != hipSuccess) return device_fail(p, e, "census clear");
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, L, B);
+        if ((e = launch_census(p->mesh, B, nqb, omega, nw, dc, p->stream)) != hipSuccess)
+            return device_fail(p, e, "census kernel");
+    }
+    unsigned long long h[4];
+    if ((e = hipMemcpyAsync(h, dc, sizeof h, hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+        return device_fail(p, e, "census copy");
+    for (int i = 0; i < 4; ++i) counts[i] = h[i];
+    return CHI0_OK;
+}
+
+chi0_status chi0_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, size_t *bytes)
+{
+    if (!p || !bytes) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || nw < 1) return fail(p, CHI0_E_INVALID_ARG, "nq and nw must be >= 1");
+    *bytes = layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch)).total;
+    return CHI0_OK;
+}
+
+chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
+    const Layout L = layout(p, nq, 1);
+    size_t need = 0;
+    chi0_workspace_size(p, nq, 1, &need);
+    if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const int nblk = n_blocks(p);
+    const int64_t upb = units_per_block(p);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, L, B);
+        hipError_t e;
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract_f64(p->mesh, B, nqb, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, nqb, upb, nblk, partial, p->stream); })) !=
+            hipSuccess)
+            return device_fail(p, e, "tetrahedron kernel");
+        if ((e = timed(p, 2, [&] { return launch_reduce(partial, nqb, nblk, 1, scale, chi + q0, 1, p->stream); })) !=
+            hipSuccess)
+            return device_fail(p, e, "reduce kernel");
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega, void *ws,
+                         size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
+    const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
+    const Layout L = layout(p, nq, 2 * nwc_max);
+    size_t need = 0;
+    chi0_workspace_size(p, nq, nw, &need);
+    if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const int nblk = n_blocks(p);
+    const int64_t upb = units_per_block(p);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, L, B);
+        hipError_t e;
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract_f64(p->mesh, B, nqb, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
+            const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
+            if ((e = timed(p, 1, [&] {
+                     return launch_tetra_dynamic(p->mesh, B, nqb, upb, nblk, omega + w0, nwc, partial, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "tetrahedron kernel");
+            if ((e = timed(p, 2, [&] {
+                     return launch_reduce(partial, nqb, nblk, 2 * nwc, scale, chi + ((int64_t)q0 * nw + w0) * 2,
+                                          (int64_t)nw * 2, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "reduce kernel");
+        }
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_matrix_elements(chi0_plan_t p, const chi0_q *q, double *W)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    if (p->d.cma) return fail(p, CHI0_E_UNSUPPORTED, "no matrix elements under cma");
+    chi0_status st = check_qs(p, 1, q);
+    if (st) return st;
+    if (!W) return fail(p, CHI0_E_INVALID_ARG, "W is null");
+    Layout L = layout(p, 1, 1);
+    BatchDev B;
+    fill_batch(p, q, 0, 1, W, L, B);
+    hipError_t e = launch_contract_f64(p->mesh, B, 1, p->stream);
+    if (e != hipSuccess) return device_fail(p, e, "matrix-element kernel");
+    return CHI0_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// chi0_internal.h -- launch interfaces shared by the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace chi0 {
+
+constexpr int kMaxQBatch = 16;     // q-points handled by one launch of each kernel
+constexpr int kWave = 64;
+constexpr int kSlots = 8;          // frequencies per lane in the dynamic kernel (8 x 64 = 512)
+constexpr int kMaxOmegaPerLaunch = kSlots * kWave;
+
+// Per-q data of one batch.
+struct QDev {
+    const double *eps_kq;   // [nb][Nk]: explicit k+q energies, or the mesh energies (shift mode)
+    const double *c_kq;     // [Nk][no][nb] complex: explicit k+q eigenvectors, or the mesh ones
+    double *W;              // [nbw][nbw][Nk] matrix elements of this q (null under CMA)
+    int32_t shift[3];       // mesh shift (0 in explicit mode)
+    int32_t explicit_kq;
+};
+
+struct BatchDev {
+    QDev q[kMaxQBatch];
+};
+
+struct MeshDev {
+    int32_t n1, n2, n3;
+    int32_t nb, no, lo, nbw;
+    int32_t cma, form;
+    int64_t nk;
+    double mu;
+    const double *eps_k;    // [nb][Nk]
+    const double *c_k;      // [Nk][no][nb] complex
+};
+
+// K_A: W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for nq q-points of a batch.
+hipError_t launch_contract_f64(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s);
+
+// K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
+hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq,
+                               int64_t units_per_block, int nblocks, double *partial, hipStream_t s);
+
+// K_B dynamic: per-block partial sums into partial[nq][nblocks][nw][2], nw <= kMaxOmegaPerLaunch.
+hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq,
+                                int64_t units_per_block, int nblocks, const double *omega, int nw,
+                                double *partial, hipStream_t s);
+
+// Census of the work of a dynamic call: counts[0..3] += active units, final tetrahedra,
+// near-branch and far-branch (final tetrahedron, frequency) evaluations.
+hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, const double *omega, int nw,
+                         unsigned long long *counts, hipStream_t s);
+
+// K_R: out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], fixed order.
+hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale,
+                         double *out, int64_t out_stride, hipStream_t s);
+
+}  // namespace chi0

@@ -1,0 +1,343 @@
+// chi0_math.h -- per-tetrahedron arithmetic of the chi0 path: double carving of a
+// mesh tetrahedron and the analytic integral of W/(w - D + i0) over a final
+// tetrahedron (Heil et al., arXiv:1407.3444, Sec. II).
+//
+// Everything here is header-only and compiles for the GPU and for the host, so
+// the same code can be exercised on the CPU by the host-side checks.
+//
+// Integral over a final tetrahedron S with corner values D_j, weights W_j:
+//   (1/|S|) int_S W / (w - D + i0) = sum_j W_j J_j,   J_j = dG/dD_j,
+//   G(D_1..D_4) = h[D_1, D_2, D_3, D_4],   h(x) = (w - x)^3 Log(w - x + i0),
+// the third divided difference of h (Hermite-Genocchi: h''' = -6 Log, and a
+// derivative with respect to a node doubles that node).  The W-weighted sum
+// is therefore the directional derivative of G along (W_1..W_4), evaluated
+// here by forward-mode differentiation of the divided-difference computation.
+//
+//  * far branch (all nodes within kRhoFar * |w - c| of their centre c):
+//    G = sum_m h^(3+m)(c)/(3+m)! H_m(D - c), H_m the complete homogeneous
+//    symmetric polynomial.  Its W-derivative is a power series in
+//    t = 1/(w - c) whose coefficients depend only on the tetrahedron, so they
+//    are computed once per tetrahedron and each frequency costs one Horner
+//    evaluation.  No logarithm, and Im = 0 (w lies outside the D range).
+//  * near branch: Newton recursion on the sorted nodes from the four
+//    logarithms, where an entry whose nodes cluster tightly compared with
+//    their distance from w is summed as a short Taylor series about its
+//    farther end node (exact for tied nodes).
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define C0_HD __host__ __device__ __forceinline__
+#else
+#define C0_HD inline
+#endif
+
+namespace chi0 {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kFarTerms = 24;          // series terms kept in the far branch
+constexpr double kRhoFar = 0.2;        // far branch when half-span <= kRhoFar * |w - c|
+constexpr double kThetaEntry = 0.25;   // Taylor sub-entry when span <= kThetaEntry * |w - x_end|
+constexpr int kTaylorMaxTerms = 48;
+
+struct cplx {
+    double re, im;
+};
+
+C0_HD cplx cmk(double r, double i) { cplx z; z.re = r; z.im = i; return z; }
+C0_HD cplx cadd(cplx a, cplx b) { return cmk(a.re + b.re, a.im + b.im); }
+C0_HD cplx csub(cplx a, cplx b) { return cmk(a.re - b.re, a.im - b.im); }
+C0_HD cplx cscale(cplx a, double s) { return cmk(a.re * s, a.im * s); }
+C0_HD cplx cfma(cplx acc, cplx a, double s) { return cmk(fma(a.re, s, acc.re), fma(a.im, s, acc.im)); }
+
+// ---------------------------------------------------------------------------
+// Carving (Sec. II: first carving by e = mu, second carving by e' = mu)
+// ---------------------------------------------------------------------------
+
+// Corner attributes carried through the carving: a = e - mu, b = e' - mu,
+// D = e' - e, W = |M|^2.  All four are linear on a tetrahedron.
+struct Vtx {
+    double a, b, D, W;
+};
+
+C0_HD Vtx vlerp(const Vtx &p, const Vtx &q, double t)
+{
+    Vtx r;
+    r.a = fma(t, q.a - p.a, p.a);
+    r.b = fma(t, q.b - p.b, p.b);
+    r.D = fma(t, q.D - p.D, p.D);
+    r.W = fma(t, q.W - p.W, p.W);
+    return r;
+}
+
+C0_HD void vswap_if(bool c, Vtx &x, Vtx &y, double &fx, double &fy)
+{
+    if (c) {
+        Vtx t = x; x = y; y = t;
+        double g = fx; fx = fy; fy = g;
+    }
+}
+
+// The clipping function f of a vertex: which attribute and with which sign.
+// KEEP_NEG_A: keep a < 0;  KEEP_POS_A: keep a > 0;  same for b.
+enum ClipKind { KEEP_NEG_A = 0, KEEP_POS_A = 1, KEEP_NEG_B = 2, KEEP_POS_B = 3 };
+
+C0_HD double clip_value(const Vtx &v, int kind)
+{
+    switch (kind) {
+    case KEEP_NEG_A: return v.a;
+    case KEEP_POS_A: return -v.a;
+    case KEEP_NEG_B: return v.b;
+    default: return -v.b;
+    }
+}
+
+// Keep the part of tetrahedron (t0..t3, volume fraction vol) where f < 0 and
+// hand each resulting tetrahedron to sink(v0, v1, v2, v3, vol).  0, 1 or 3 pieces.
+// Volume fractions are products of the edge parameters, never determinants.
+template <class Sink>
+C0_HD void clip_neg(Vtx t0, Vtx t1, Vtx t2, Vtx t3, double vol, int kind, Sink &sink)
+{
+    double f0 = clip_value(t0, kind), f1 = clip_value(t1, kind);
+    double f2 = clip_value(t2, kind), f3 = clip_value(t3, kind);
+    // partition: inside (f < 0) vertices first (a sorting network on the key f >= 0)
+    vswap_if(f0 >= 0.0 && f1 < 0.0, t0, t1, f0, f1);
+    vswap_if(f2 >= 0.0 && f3 < 0.0, t2, t3, f2, f3);
+    vswap_if(f0 >= 0.0 && f2 < 0.0, t0, t2, f0, f2);
+    vswap_if(f1 >= 0.0 && f3 < 0.0, t1, t3, f1, f3);
+    vswap_if(f1 >= 0.0 && f2 < 0.0, t1, t2, f1, f2);
+    const int nin = (f0 < 0.0) + (f1 < 0.0) + (f2 < 0.0) + (f3 < 0.0);
+    if (nin == 0) return;
+    if (nin == 4) { sink(t0, t1, t2, t3, vol); return; }
+    if (nin == 1) {
+        // corner tetrahedron at t0; s_k = fraction of edge t0->tk
+        const double s1 = f0 / (f0 - f1), s2 = f0 / (f0 - f2), s3 = f0 / (f0 - f3);
+        sink(t0, vlerp(t0, t1, s1), vlerp(t0, t2, s2), vlerp(t0, t3, s3), vol * s1 * s2 * s3);
+        return;
+    }
+    if (nin == 3) {
+        // tetrahedron minus the corner at t3: prism (t0,t1,t2 | P0,P1,P2), P_i on edge t_i->t3
+        const double s0 = f0 / (f0 - f3), s1 = f1 / (f1 - f3), s2 = f2 / (f2 - f3);
+        const double r0 = f3 / (f3 - f0), r1 = f3 / (f3 - f1);   // 1 - s_i without cancellation
+        const Vtx P0 = vlerp(t0, t3, s0), P1 = vlerp(t1, t3, s1), P2 = vlerp(t2, t3, s2);
+        sink(t0, t1, t2, P0, vol * s0);
+        sink(t1, t2, P0, P1, vol * r0 * s1);
+        sink(t2, P0, P1, P2, vol * r0 * r1 * s2);
+        return;
+    }
+    // nin == 2: prism with ends (t0, P02, P03) and (t1, P12, P13)
+    const double s02 = f0 / (f0 - f2), s03 = f0 / (f0 - f3);
+    const double s12 = f1 / (f1 - f2), s13 = f1 / (f1 - f3);
+    const double r02 = f2 / (f2 - f0), r03 = f3 / (f3 - f0);       // 1 - s02, 1 - s03
+    const Vtx P02 = vlerp(t0, t2, s02), P03 = vlerp(t0, t3, s03);
+    const Vtx P12 = vlerp(t1, t2, s12), P13 = vlerp(t1, t3, s13);
+    sink(t0, P02, P03, t1, vol * s02 * s03);
+    sink(P02, P03, t1, P12, vol * s03 * s12 * r02);
+    sink(P03, t1, P12, P13, vol * r03 * s12 * s13);
+}
+
+// Second carving stage: forwards every piece clipped by the second function.
+template <class Sink>
+struct SecondClip {
+    int kind;
+    Sink *out;
+    C0_HD void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
+    {
+        clip_neg(v0, v1, v2, v3, vol, kind, *out);
+    }
+};
+
+// Region 1 = {e < mu < e'} (n occupied at k, m empty at k+q); region 2 = {e' < mu < e}.
+template <class Sink>
+C0_HD void carve_region(const Vtx &t0, const Vtx &t1, const Vtx &t2, const Vtx &t3, int region,
+                        Sink &sink)
+{
+    SecondClip<Sink> second;
+    second.kind = region == 1 ? KEEP_POS_B : KEEP_NEG_B;
+    second.out = &sink;
+    clip_neg(t0, t1, t2, t3, 1.0, region == 1 ? KEEP_NEG_A : KEEP_POS_A, second);
+}
+
+// Quick tests on the corner values before any carving.
+C0_HD bool region_empty(const Vtx &t0, const Vtx &t1, const Vtx &t2, const Vtx &t3, int region)
+{
+    if (region == 1)
+        return (t0.a >= 0.0 && t1.a >= 0.0 && t2.a >= 0.0 && t3.a >= 0.0) ||
+               (t0.b <= 0.0 && t1.b <= 0.0 && t2.b <= 0.0 && t3.b <= 0.0);
+    return (t0.a <= 0.0 && t1.a <= 0.0 && t2.a <= 0.0 && t3.a <= 0.0) ||
+           (t0.b >= 0.0 && t1.b >= 0.0 && t2.b >= 0.0 && t3.b >= 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Final-tetrahedron weights
+// ---------------------------------------------------------------------------
+
+// Sort the four (D, W) pairs by D ascending (5 compare-exchanges).
+C0_HD void sort4(double y[4], double w[4])
+{
+#define C0_CX(i, j)                                                         \
+    if (y[j] < y[i]) {                                                      \
+        double ty = y[i]; y[i] = y[j]; y[j] = ty;                           \
+        double tw = w[i]; w[i] = w[j]; w[j] = tw;                           \
+    }
+    C0_CX(0, 1) C0_CX(2, 3) C0_CX(0, 2) C0_CX(1, 3) C0_CX(1, 2)
+#undef C0_CX
+}
+
+// Far-branch coefficients: sum_j W_j J_j = sum_{m=1..K} a[m-1] t^m, t = 1/(w - c),
+// a_m = 6/(m(m+1)(m+2)(m+3)) * d/dW H_m(D - c)   (valid for half-span < |w - c|).
+C0_HD void far_coeffs(const double y[4], const double w[4], double c, double *a)
+{
+    double z0 = y[0] - c, z1 = y[1] - c, z2 = y[2] - c, z3 = y[3] - c;
+    double P0 = 1.0, P1 = 1.0, P2 = 1.0, P3 = 1.0;      // H_{m-1} over growing variable sets
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;      // their W-derivatives
+    for (int m = 1; m <= kFarTerms; ++m) {
+        double n0 = z0 * P0;
+        double e0 = fma(w[0], P0, z0 * d0);
+        double n1 = fma(z1, P1, n0);
+        double e1 = fma(w[1], P1, fma(z1, d1, e0));
+        double n2 = fma(z2, P2, n1);
+        double e2 = fma(w[2], P2, fma(z2, d2, e1));
+        double n3 = fma(z3, P3, n2);
+        double e3 = fma(w[3], P3, fma(z3, d3, e2));
+        P0 = n0; P1 = n1; P2 = n2; P3 = n3;
+        d0 = e0; d1 = e1; d2 = e2; d3 = e3;
+        const double mm = (double)m;
+        a[m - 1] = 6.0 / (mm * (mm + 1.0) * (mm + 2.0) * (mm + 3.0)) * e3;
+    }
+}
+
+C0_HD double far_horner(const double *a, double t)
+{
+    double s = a[kFarTerms - 1];
+#pragma unroll
+    for (int m = kFarTerms - 2; m >= 0; --m) s = fma(s, t, a[m]);
+    return s * t;
+}
+
+// h^(n)/n! (x-derivatives of h(x) = u^3 L, u = w - x, L = Log(u + i0)) for n <= 3.
+C0_HD cplx hder_low(int n, double u, cplx L)
+{
+    switch (n) {
+    case 0: { double u3 = u * u * u; return cmk(u3 * L.re, u3 * L.im); }
+    case 1: { double u2 = u * u; return cmk(-(3.0 * u2 * L.re + u2), -3.0 * u2 * L.im); }
+    case 2: return cmk(3.0 * u * L.re + 2.5 * u, 3.0 * u * L.im);
+    default: return cmk(-(L.re + 11.0 / 6.0), -L.im);
+    }
+}
+
+// Value and W-derivative of the divided difference h[y_i..y_j] (p = j - i) as a
+// Taylor series about the node y_k (k = i or j): sum_m h^(p+m)(y_k)/(p+m)! H_m(y - y_k).
+C0_HD void taylor_entry(const double *y, const double *w, int i, int j, int k, double om, cplx Lk,
+                        cplx &val, cplx &tan)
+{
+    const int p = j - i;
+    const double u = om - y[k];
+    const double inv = 1.0 / u;
+    double z[4], dz[4];
+    double rho = 0.0;
+    for (int v = 0; v <= p; ++v) {
+        z[v] = (y[i + v] - y[k]) * inv;      // offsets in units of u
+        dz[v] = w[i + v] * inv;
+        rho = fmax(rho, fabs(z[v]));
+    }
+    // H_m(z) and its derivative, over the growing variable set, term by term
+    double P[4], dP[4];
+    for (int v = 0; v <= p; ++v) { P[v] = 1.0; dP[v] = 0.0; }
+    const double up = (p == 4) ? inv : (p == 3 ? 1.0 : (p == 2 ? u : u * u));   // u^(3-p), p in 1..3
+    double um = 1.0;                        // u^m for the low-order (logarithmic) terms
+    val = cmk(0.0, 0.0);
+    tan = cmk(0.0, 0.0);
+    double bound = 1.0;                     // C(m+p, p) rho^m
+    for (int m = 0; m < kTaylorMaxTerms; ++m) {
+        double H = 1.0, dH = 0.0;
+        if (m > 0) {
+            double prev = 0.0, dprev = 0.0;
+            for (int v = 0; v <= p; ++v) {
+                const double nP = fma(z[v], P[v], prev);
+                const double ndP = fma(dz[v], P[v], fma(z[v], dP[v], dprev));
+                P[v] = nP; dP[v] = ndP;
+                prev = nP; dprev = ndP;
+            }
+            H = prev; dH = dprev;
+        }
+        const int n = p + m;
+        if (n >= 4) {
+            const double nn = (double)n;
+            const double cf = 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0)) * up;
+            val.re = fma(cf, H, val.re);
+            tan.re = fma(cf, dH, tan.re);
+        } else {
+            const cplx hd = hder_low(n, u, Lk);
+            val = cfma(val, hd, um * H);
+            tan = cfma(tan, hd, um * dH);
+            um *= u;
+        }
+        bound *= (double)(m + p + 1) / (double)(m + 1) * rho;
+        if (m >= 4 && bound < 1e-17) break;
+    }
+}
+
+// Near branch: sum_j W_j J_j at frequency om for sorted nodes y with weights w.
+C0_HD cplx near_eval(const double y[4], const double w[4], double om)
+{
+    cplx V[4][4], T[4][4];            // value / W-derivative of h[y_i..y_j], i <= j
+    cplx L[4];
+    double u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        u[i] = om - y[i];
+        if (u[i] == 0.0) {            // h and h' vanish at u = 0
+            L[i] = cmk(0.0, 0.0);
+            V[i][i] = cmk(0.0, 0.0);
+            T[i][i] = cmk(0.0, 0.0);
+        } else {
+            L[i] = cmk(log(fabs(u[i])), u[i] < 0.0 ? kPi : 0.0);
+            V[i][i] = hder_low(0, u[i], L[i]);
+            T[i][i] = cscale(hder_low(1, u[i], L[i]), w[i]);
+        }
+    }
+#pragma unroll
+    for (int p = 1; p < 4; ++p) {
+#pragma unroll
+        for (int i = 0; i + p < 4; ++i) {
+            const int j = i + p;
+            const double span = y[j] - y[i];
+            const double di = fabs(u[i]), dj = fabs(u[j]);
+            const double far = fmax(di, dj);
+            if (span <= kThetaEntry * far) {
+                const int k = di >= dj ? i : j;
+                taylor_entry(y, w, i, j, k, om, k == i ? L[i] : L[j], V[i][j], T[i][j]);
+            } else {
+                const double inv = 1.0 / span;
+                const cplx E = cscale(csub(V[i + 1][j], V[i][j - 1]), inv);
+                const double dspan = (w[j] - w[i]) * inv;
+                cplx dE = cscale(csub(T[i + 1][j], T[i][j - 1]), inv);
+                dE = cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
+                V[i][j] = E;
+                T[i][j] = dE;
+            }
+        }
+    }
+    return T[0][3];
+}
+
+// sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.
+C0_HD cplx tetra_weight_sum(const double D[4], const double Wt[4], double om)
+{
+    double y[4] = {D[0], D[1], D[2], D[3]}, w[4] = {Wt[0], Wt[1], Wt[2], Wt[3]};
+    sort4(y, w);
+    const double c = 0.5 * (y[0] + y[3]), r = 0.5 * (y[3] - y[0]);
+    const double d = om - c;
+    if (r <= kRhoFar * fabs(d)) {
+        double a[kFarTerms];
+        far_coeffs(y, w, c, a);
+        return cmk(far_horner(a, 1.0 / d), 0.0);
+    }
+    return near_eval(y, w, om);
+}
+
+}  // namespace chi0

@@ -1,0 +1,105 @@
+// k_contract.hip -- matrix elements on the FP64 matrix cores (K_A).
+//
+// For every mesh point k of a q:  M_nm = sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)  and
+// W_nm(k) = |M_nm|^2 (the tight-binding matrix element of the footnote in Sec. III).
+// Per k this is a small complex GEMM (bands x orbitals) x (orbitals x bands); it
+// runs as real 16x16x4 FP64 MFMAs (v_mfma_f64_16x16x4f64), four per step of 4
+// orbitals:  Re M = Cr^T Br + Ci^T Bi,  Im M = Cr^T Bi - Ci^T Br.
+// A workgroup is one wave that handles 16 consecutive k; |M|^2 of a 16x16 band
+// tile is staged in LDS as [n][m][k] and written out pair-major, so each store
+// covers 16 consecutive k of one band pair (the layout the tetrahedron kernel
+// reads with consecutive lanes on consecutive cells).
+#include "chi0_internal.h"
+
+namespace chi0 {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kKPerBlock = 16;
+
+__global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B)
+{
+    __shared__ double tile[16][16][kKPerBlock + 1];
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int lane = threadIdx.x;
+    const int row = lane & 15;      // A row (band n) / B column (band m) of this lane
+    const int kk = lane >> 4;       // orbital within the step of 4
+    const int64_t nk = M.nk;
+    const int64_t k0 = (int64_t)blockIdx.x * kKPerBlock;
+    const int ntile = (M.nbw + 15) / 16;
+    const int nb = M.nb, no = M.no;
+
+    for (int tn = 0; tn < ntile; ++tn) {
+        for (int tm = 0; tm < ntile; ++tm) {
+            const int n = tn * 16 + row;
+            const int m = tm * 16 + row;
+            for (int kl = 0; kl < kKPerBlock; ++kl) {
+                const int64_t k = k0 + kl;
+                if (k >= nk) break;
+                int64_t kq = k;
+                if (!Q.explicit_kq) {
+                    int i2 = (int)(k % M.n3);
+                    const int64_t t = k / M.n3;
+                    int i1 = (int)(t % M.n2);
+                    int i0 = (int)(t / M.n2);
+                    i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
+                    i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
+                    i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
+                    kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
+                }
+                dbl4 accr = {0.0, 0.0, 0.0, 0.0};
+                dbl4 acci = {0.0, 0.0, 0.0, 0.0};
+                for (int o0 = 0; o0 < no; o0 += 4) {
+                    const int o = o0 + kk;
+                    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+                    if (o < no && n < M.nbw) {
+                        const double *p = M.c_k + 2 * ((k * no + o) * nb + M.lo + n);
+                        ar = p[0];
+                        ai = p[1];
+                    }
+                    if (o < no && m < M.nbw) {
+                        const double *p = Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m);
+                        br = p[0];
+                        bi = p[1];
+                    }
+                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
+                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, accr, 0, 0, 0);
+                    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
+                    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, acci, 0, 0, 0);
+                }
+                // accumulator element v of this lane is D[kk + 4 v][row] (row index = band n,
+                // column = band m) for the FP64 16x16x4 MFMA
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    tile[kk + 4 * v][row][kl] = accr[v] * accr[v] + acci[v] * acci[v];
+            }
+            __syncthreads();
+            for (int e = lane; e < 16 * 16 * kKPerBlock; e += 64) {
+                const int kl = e % kKPerBlock;
+                const int pj = e / kKPerBlock;
+                const int i = pj / 16, j = pj % 16;
+                const int nn = tn * 16 + i, mm = tm * 16 + j;
+                const int64_t k = k0 + kl;
+                if (nn < M.nbw && mm < M.nbw && k < nk)
+                    Q.W[((int64_t)nn * M.nbw + mm) * nk + k] = tile[i][j][kl];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_contract_f64(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s)
+{
+    if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;
+    dim3 grid((unsigned)nblk, nq), block(64);
+    hipLaunchKernelGGL(contract_f64_kernel, grid, block, 0, s, mesh, batch);
+    return hipGetLastError();
+}
+
+}  // namespace chi0

@@ -1,0 +1,420 @@
+// k_tetra.hip -- the tetrahedron kernel of the chi0 path (K_B).
+//
+// One work unit is one (mesh tetrahedron, band pair) of one q.  A workgroup is
+// one 64-lane wave that owns a contiguous range of units.  Each round, every
+// lane takes one unit, loads the 4 corner values of e = eps_n(k),
+// e' = eps_m(k+q) and W_nm(k) (coalesced: consecutive lanes hold consecutive
+// cells), carves it into final tetrahedra -- first by e = mu, then by
+// e' = mu (Sec. II) -- and appends them to a list in LDS at an offset from a
+// wave prefix sum (so the order, and with it every FP64 sum, is fixed).
+//
+//  * dynamic: every final tetrahedron is then evaluated by all 64 lanes, each
+//    lane owning up to 8 frequencies (lane + 64 s).  Far-cluster tetrahedra
+//    cost one Horner evaluation per frequency from coefficients computed once
+//    (spread over the lanes) and stored with the tetrahedron in LDS; only
+//    frequencies inside a tetrahedron's near window pay for logarithms.
+//    Lanes accumulate their own frequencies, so no cross-lane reduction.
+//  * static (w = 0): lanes split the list instead, and the wave reduces its
+//    lane sums with a fixed butterfly at the end.
+//
+// Each workgroup writes its partial sums; the reduce kernel (K_R) adds them in
+// block order.
+#include "chi0_internal.h"
+#include "chi0_math.h"
+
+namespace chi0 {
+
+namespace {
+
+constexpr int kCapDyn = 64;     // final tetrahedra per LDS list (dynamic)
+constexpr int kCapStat = 192;   // final tetrahedra per LDS list (static)
+
+struct DynRec {
+    double y[4];                // D at the corners (sorted ascending after the prep pass)
+    double w[4];                // sign * volume * W at the same corners
+    double c, r;                // centre and half-span of the D range
+    double a[kFarTerms];        // far-branch series coefficients
+};
+
+struct StatRec {
+    double D[4];
+    double w[4];
+};
+
+constexpr int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    // hardware dispatches block b to XCD b % 8; give each XCD a contiguous run of
+    // logical blocks so neighbouring cells share that XCD's L2
+    const int per = nblocks / 8, rem = nblocks % 8;
+    const int x = b % 8, j = b / 8;
+    return x * per + min(x, rem) + j;
+}
+
+__device__ __forceinline__ int wrap_inc(int i, int n) { return i + 1 == n ? 0 : i + 1; }
+
+// Corner values of unit u (pair-major, then tetrahedron permutation, then cell).
+__device__ __forceinline__ void load_unit(const MeshDev &M, const QDev &Q, int64_t u, Vtx t[4])
+{
+    const int64_t nk = M.nk;
+    const int64_t per_pair = 6 * nk;
+    const int pair = (int)(u / per_pair);
+    const int64_t rem = u - (int64_t)pair * per_pair;
+    const int perm = (int)(rem / nk);
+    const int64_t cell = rem - (int64_t)perm * nk;
+    const int n = pair / M.nbw, m = pair - n * M.nbw;
+    int i[3];
+    i[2] = (int)(cell % M.n3);
+    const int64_t c12 = cell / M.n3;
+    i[1] = (int)(c12 % M.n2);
+    i[0] = (int)(c12 / M.n2);
+    const int nn[3] = {M.n1, M.n2, M.n3};
+    const double *ek = M.eps_k + (int64_t)(M.lo + n) * nk;
+    const double *ekq = Q.eps_kq + (int64_t)(M.lo + m) * nk;
+    const double *Wp = M.cma ? nullptr : Q.W + (int64_t)pair * nk;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c > 0) {
+            const int ax = kPerm[perm][c - 1];
+            i[ax] = wrap_inc(i[ax], nn[ax]);
+        }
+        const int64_t idx = ((int64_t)i[0] * M.n2 + i[1]) * M.n3 + i[2];
+        int64_t idq = idx;
+        if (!Q.explicit_kq) {
+            int j0 = i[0] + Q.shift[0], j1 = i[1] + Q.shift[1], j2 = i[2] + Q.shift[2];
+            j0 -= j0 >= M.n1 ? M.n1 : 0;
+            j1 -= j1 >= M.n2 ? M.n2 : 0;
+            j2 -= j2 >= M.n3 ? M.n3 : 0;
+            idq = ((int64_t)j0 * M.n2 + j1) * M.n3 + j2;
+        }
+        const double e = ek[idx], ep = ekq[idq];
+        t[c].a = e - M.mu;
+        t[c].b = ep - M.mu;
+        t[c].D = ep - e;
+        t[c].W = M.cma ? 1.0 : Wp[idx];
+    }
+}
+
+struct CountSink {
+    int n;
+    int mult;
+    __device__ void operator()(const Vtx &, const Vtx &, const Vtx &, const Vtx &, double vol)
+    {
+        n += (vol != 0.0) ? mult : 0;
+    }
+};
+
+// Appends final tetrahedra as (D, sign*vol*W); with form 1 also (-D, -sign*vol*W).
+template <class Rec>
+struct WriteSink {
+    Rec *list;
+    int pos;
+    int limit;     // one past the last slot counted for this unit: never written beyond
+    double sign;
+    int form;
+    __device__ void put(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double s, bool neg)
+    {
+        if (pos >= limit) return;
+        Rec &r = list[pos++];
+        const double g = neg ? -1.0 : 1.0;
+        r.y[0] = g * v0.D; r.y[1] = g * v1.D; r.y[2] = g * v2.D; r.y[3] = g * v3.D;
+        r.w[0] = s * v0.W; r.w[1] = s * v1.W; r.w[2] = s * v2.W; r.w[3] = s * v3.W;
+    }
+    __device__ void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
+    {
+        if (vol == 0.0) return;
+        put(v0, v1, v2, v3, sign * vol, false);
+        if (form == 1) put(v0, v1, v2, v3, -sign * vol, true);
+    }
+};
+
+template <>
+__device__ void WriteSink<StatRec>::put(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3,
+                                        double s, bool neg)
+{
+    if (pos >= limit) return;
+    StatRec &r = list[pos++];
+    const double g = neg ? -1.0 : 1.0;
+    r.D[0] = g * v0.D; r.D[1] = g * v1.D; r.D[2] = g * v2.D; r.D[3] = g * v3.D;
+    r.w[0] = s * v0.W; r.w[1] = s * v1.W; r.w[2] = s * v2.W; r.w[3] = s * v3.W;
+}
+
+__device__ __forceinline__ int count_unit(const Vtx t[4], int form)
+{
+    CountSink cs;
+    cs.n = 0;
+    cs.mult = form == 1 ? 2 : 1;
+    if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, cs);
+    if (form == 0) {
+        cs.mult = 1;
+        if (!region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
+    }
+    return cs.n;
+}
+
+template <class Rec>
+__device__ __forceinline__ void write_unit(const Vtx t[4], int form, Rec *list, int pos, int limit)
+{
+    WriteSink<Rec> ws;
+    ws.list = list;
+    ws.pos = pos;
+    ws.limit = limit;
+    ws.form = form;
+    ws.sign = 1.0;
+    if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, ws);
+    if (form == 0) {
+        ws.sign = -1.0;
+        if (!region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, ws);
+    }
+}
+
+__device__ __forceinline__ int wave_inclusive_scan(int x, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Fill the LDS list with the final tetrahedra of lanes [start, next) of this round.
+// Returns the number of records; next_out receives the first lane left for a later pass.
+template <class Rec, int CAP>
+__device__ __forceinline__ int fill_list(const Vtx t[4], bool valid, int cnt, int start, int lane,
+                                         int form, Rec *list, int &next_out)
+{
+    const int c = (lane >= start) ? cnt : 0;
+    const int incl = wave_inclusive_scan(c, lane);
+    const int excl = incl - c;
+    const bool fits = lane >= start && incl <= CAP;
+    const unsigned long long mask = __ballot(fits);
+    const int next = start + __popcll(mask);
+    const int nrec = __shfl(incl, next - 1, kWave);
+    if (fits && valid && cnt > 0) write_unit<Rec>(t, form, list, excl, incl);
+    next_out = next;
+    return nrec;
+}
+
+template <int NSLOT>
+__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int64_t upb, int nblocks,
+                                                           const double *__restrict__ omega, int nw,
+                                                           double *__restrict__ partial)
+{
+    __shared__ DynRec list[kCapDyn];
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int lane = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, nblocks);
+    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const int64_t u0 = (int64_t)blk * upb;
+    const int64_t u1 = min(u0 + upb, n_units);
+
+    double om[NSLOT];
+    cplx acc[NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int idx = lane + kWave * s;
+        om[s] = omega[idx < nw ? idx : nw - 1];
+        acc[s] = cmk(0.0, 0.0);
+    }
+
+    for (int64_t base = u0; base < u1; base += kWave) {
+        const int64_t u = base + lane;
+        const bool valid = u < u1;
+        Vtx t[4];
+        int cnt = 0;
+        if (valid) {
+            load_unit(M, Q, u, t);
+            cnt = count_unit(t, M.form);
+        }
+        int start = 0;
+        while (start < kWave) {
+            int next;
+            const int nrec = fill_list<DynRec, kCapDyn>(t, valid, cnt, start, lane, M.form, list, next);
+            start = next;
+            if (nrec == 0) continue;
+            __syncthreads();
+            // per-tetrahedron preparation, spread over the lanes
+            for (int r = lane; r < nrec; r += kWave) {
+                double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
+                double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
+                sort4(y, w);
+                const double c = 0.5 * (y[0] + y[3]);
+                double a[kFarTerms];
+                far_coeffs(y, w, c, a);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
+                list[r].c = c;
+                list[r].r = 0.5 * (y[3] - y[0]);
+#pragma unroll
+                for (int k = 0; k < kFarTerms; ++k) list[r].a[k] = a[k];
+            }
+            __syncthreads();
+            for (int r = 0; r < nrec; ++r) {
+                double y[4], w[4], a[kFarTerms];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
+                const double c = list[r].c, hs = list[r].r;
+#pragma unroll
+                for (int k = 0; k < kFarTerms; ++k) a[k] = list[r].a[k];
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) {
+                    const double d = om[s] - c;
+                    if (hs <= kRhoFar * fabs(d)) {
+                        acc[s].re += far_horner(a, 1.0 / d);
+                    } else {
+                        acc[s] = cadd(acc[s], near_eval(y, w, om[s]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int idx = lane + kWave * s;
+        if (idx < nw) {
+            double *p = partial + (((int64_t)qi * nblocks + blk) * nw + idx) * 2;
+            p[0] = acc[s].re;
+            p[1] = acc[s].im;
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int64_t upb, int nblocks,
+                                                          double *__restrict__ partial)
+{
+    __shared__ StatRec list[kCapStat];
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int lane = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, nblocks);
+    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const int64_t u0 = (int64_t)blk * upb;
+    const int64_t u1 = min(u0 + upb, n_units);
+    double acc = 0.0;
+    for (int64_t base = u0; base < u1; base += kWave) {
+        const int64_t u = base + lane;
+        const bool valid = u < u1;
+        Vtx t[4];
+        int cnt = 0;
+        if (valid) {
+            load_unit(M, Q, u, t);
+            cnt = count_unit(t, M.form);
+        }
+        int start = 0;
+        while (start < kWave) {
+            int next;
+            const int nrec = fill_list<StatRec, kCapStat>(t, valid, cnt, start, lane, M.form, list, next);
+            start = next;
+            if (nrec == 0) continue;
+            __syncthreads();
+            for (int r = lane; r < nrec; r += kWave) {
+                const double D[4] = {list[r].D[0], list[r].D[1], list[r].D[2], list[r].D[3]};
+                const double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
+                acc += tetra_weight_sum(D, w, 0.0).re;
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+    if (lane == 0) partial[(int64_t)qi * nblocks + blk] = acc;
+}
+
+// Work census (diagnostic, untimed): counts, over all units of the batch, the units with
+// a non-empty carved region, the final tetrahedra, and the (final tetrahedron, frequency)
+// evaluations that take the near branch and the far branch of the weight evaluation.
+struct CensusSink {
+    const double *omega;
+    int nw;
+    int form;
+    unsigned long long n_tet, n_near, n_far;
+    __device__ void one(const double D0, const double D1, const double D2, const double D3)
+    {
+        double y[4] = {D0, D1, D2, D3}, w[4] = {0.0, 0.0, 0.0, 0.0};
+        sort4(y, w);
+        const double c = 0.5 * (y[0] + y[3]), r = 0.5 * (y[3] - y[0]);
+        unsigned long long nn = 0;
+        for (int i = 0; i < nw; ++i) nn += (r <= kRhoFar * fabs(omega[i] - c)) ? 0ull : 1ull;
+        n_tet += 1;
+        n_near += nn;
+        n_far += (unsigned long long)nw - nn;
+    }
+    __device__ void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
+    {
+        if (vol == 0.0) return;
+        one(v0.D, v1.D, v2.D, v3.D);
+        if (form == 1) one(-v0.D, -v1.D, -v2.D, -v3.D);
+    }
+};
+
+__global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, const double *__restrict__ omega, int nw,
+                                                     unsigned long long *__restrict__ counts)
+{
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    CensusSink cs;
+    cs.omega = omega;
+    cs.nw = nw;
+    cs.form = M.form;
+    cs.n_tet = cs.n_near = cs.n_far = 0;
+    unsigned long long active = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        Vtx t[4];
+        load_unit(M, Q, u, t);
+        const unsigned long long before = cs.n_tet;
+        if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, cs);
+        if (M.form == 0 && !region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
+        active += cs.n_tet > before ? 1ull : 0ull;
+    }
+    atomicAdd(&counts[0], active);
+    atomicAdd(&counts[1], cs.n_tet);
+    atomicAdd(&counts[2], cs.n_near);
+    atomicAdd(&counts[3], cs.n_far);
+}
+
+}  // namespace
+
+hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int64_t units_per_block,
+                                int nblocks, const double *omega, int nw, double *partial, hipStream_t s)
+{
+    if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nq), block(kWave);
+    const int slots = (nw + kWave - 1) / kWave;
+    switch (slots) {
+#define C0_CASE(S)                                                                                       \
+    case S:                                                                                              \
+        hipLaunchKernelGGL(tetra_dynamic_kernel<S>, grid, block, 0, s, mesh, batch, units_per_block,     \
+                           nblocks, omega, nw, partial);                                                 \
+        break;
+        C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
+#undef C0_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, const double *omega, int nw,
+                         unsigned long long *counts, hipStream_t s)
+{
+    if (nq < 1 || nq > kMaxQBatch || nw < 1) return hipErrorInvalidValue;
+    dim3 grid(1024, nq), block(256);
+    hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int64_t units_per_block,
+                               int nblocks, double *partial, hipStream_t s)
+{
+    if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nq), block(kWave);
+    hipLaunchKernelGGL(tetra_static_kernel, grid, block, 0, s, mesh, batch, units_per_block, nblocks, partial);
+    return hipGetLastError();
+}
+
+}  // namespace chi0

@@ -286,8 +286,20 @@ def _explicit_q(model: TBModel, kf: np.ndarray, q: np.ndarray) -> QPoint:
     return QPoint(q_frac=np.asarray(q, dtype=np.float64), eps_kq=e, c_kq=c)
 
 
+def _explicit_qs(model: TBModel, kf: np.ndarray, qlist, workers: int = 1) -> List[QPoint]:
+    """Explicit k+q eigensystems for every q (optionally in worker processes; same bytes)."""
+    qlist = [np.asarray(q, dtype=np.float64) for q in qlist]
+    if workers <= 1 or len(qlist) <= 1:
+        return [_explicit_q(model, kf, q) for q in qlist]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_explicit_q, [model] * len(qlist), [kf] * len(qlist), qlist))
+
+
 def make_workload(name: str, nk=None, nq: Optional[int] = None, nw: Optional[int] = None,
-                  q_subset: Optional[Sequence[int]] = None, n_keep: Optional[int] = None) -> Workload:
+                  q_subset: Optional[Sequence[int]] = None, n_keep: Optional[int] = None,
+                  workers: int = 1) -> Workload:
     """Build one of the seeded workloads.
 
     name:
@@ -299,7 +311,8 @@ def make_workload(name: str, nk=None, nq: Optional[int] = None, nw: Optional[int
                       omega on [0, 2] eV; default mesh 48^3, 64 q x 512 omega, band window n_keep.
       'tetra_dynamic' the 'tetra_static' model at 64 q (midpoints of the same path) x 512 omega.
     nk / nq / nw override the mesh, number of q on the path and omega count (smaller test sizes);
-    q_subset keeps only those indices of the q-list (the k+q eigensystems are only built for them).
+    q_subset keeps only those indices of the q-list (the k+q eigensystems are only built for them);
+    workers > 1 builds the k+q eigensystems in that many processes (identical results).
     """
     if name == "sc_cma":
         nk = tuple(nk or (16, 16, 16))
@@ -331,7 +344,7 @@ def make_workload(name: str, nk=None, nq: Optional[int] = None, nw: Optional[int
         eps, c = eigensystem(model, kf)
         qlist = gamma_x_m_gamma_midpoints(nq or (64 if dyn else 256))
         idx = range(len(qlist)) if q_subset is None else q_subset
-        qs = [_explicit_q(model, kf, qlist[i]) for i in idx]
+        qs = _explicit_qs(model, kf, [qlist[i] for i in idx], workers)
         omega = omega_grid(nw or 512) if dyn else np.zeros(1)
         return Workload(name, nk, eps, c, qs, omega, static=not dyn,
                         meta={"model": "tetragonal_two_site", "seed": 2, "q_index": list(idx)})
@@ -342,7 +355,7 @@ def make_workload(name: str, nk=None, nq: Optional[int] = None, nw: Optional[int
         eps, c = eigensystem(model, kf)
         qlist = bcc_gamma_h_gamma_path(nq or 64)
         idx = range(len(qlist)) if q_subset is None else q_subset
-        qs = [_explicit_q(model, kf, qlist[i]) for i in idx]
+        qs = _explicit_qs(model, kf, [qlist[i] for i in idx], workers)
         lo, hi = band_window(eps, n_keep or 9)
         return Workload(name, nk, eps, c, qs, omega_grid(nw or 512), band_lo=lo, band_hi=hi,
                         meta={"model": "bcc_spd", "seed": 3, "q_index": list(idx), "n_keep": n_keep or 9})

@@ -1,0 +1,66 @@
+// Host build of the GPU path's per-tetrahedron arithmetic (chi0_math.h), for CPU checks
+// against the oracle.  Test infrastructure: the product library does not use it.
+#include "../../paper_1407_3444_amd/csrc/chi0_math.h"
+
+using namespace chi0;
+
+namespace {
+struct Acc {
+    double om;
+    int form;
+    double sign;
+    cplx sum;
+    int npieces;
+    void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
+    {
+        if (vol == 0.0) return;
+        ++npieces;
+        double D[4] = {v0.D, v1.D, v2.D, v3.D};
+        double W[4] = {sign * vol * v0.W, sign * vol * v1.W, sign * vol * v2.W, sign * vol * v3.W};
+        sum = cadd(sum, tetra_weight_sum(D, W, om));
+        if (form == 1) {
+            double Dm[4] = {-D[0], -D[1], -D[2], -D[3]};
+            double Wm[4] = {-W[0], -W[1], -W[2], -W[3]};
+            sum = cadd(sum, tetra_weight_sum(Dm, Wm, om));
+        }
+    }
+};
+}  // namespace
+
+extern "C" {
+
+// sum_j W_j J_j(w; D) for one final tetrahedron; out = (re, im)
+void hc_weight_sum(const double *D, const double *W, double om, double *out)
+{
+    cplx z = tetra_weight_sum(D, W, om);
+    out[0] = z.re;
+    out[1] = z.im;
+}
+
+// contribution of one (tetrahedron, band pair): corner a = e - mu, b = e' - mu, W; form 0/1.
+// out = (re, im); returns the number of final tetrahedra.
+int hc_unit(const double *a, const double *b, const double *W, double om, int form, double *out)
+{
+    Vtx t[4];
+    for (int c = 0; c < 4; ++c) {
+        t[c].a = a[c];
+        t[c].b = b[c];
+        t[c].D = b[c] - a[c];
+        t[c].W = W[c];
+    }
+    Acc acc;
+    acc.om = om;
+    acc.form = form;
+    acc.sum = cmk(0.0, 0.0);
+    acc.npieces = 0;
+    acc.sign = 1.0;
+    if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, acc);
+    if (form == 0) {
+        acc.sign = -1.0;
+        if (!region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, acc);
+    }
+    out[0] = acc.sum.re;
+    out[1] = acc.sum.im;
+    return acc.npieces;
+}
+}

@@ -1,0 +1,121 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the header
+declares, and rejects bad descriptors and arguments on the host with the documented
+status codes (no device call is made on these paths)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1407_3444_amd as lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chi0.h")
+
+
+def _header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(chi0_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert sorted(lib.EXPORTED_SYMBOLS) == _header_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    so = lib.load_library()
+    for name in _header_functions():
+        assert hasattr(so, name), name
+
+
+def _desc(**kw):
+    d = lib._Desc()
+    d.nk[0], d.nk[1], d.nk[2] = kw.get("nk", (4, 4, 4))
+    d.n_bands = kw.get("n_bands", 4)
+    d.n_orb = kw.get("n_orb", 4)
+    d.band_lo = kw.get("band_lo", 0)
+    d.band_hi = kw.get("band_hi", 0)
+    d.cma = kw.get("cma", 0)
+    d.form = kw.get("form", 0)
+    d.precision = kw.get("precision", 0)
+    d.mu = kw.get("mu", 0.0)
+    d.spin_factor = kw.get("spin_factor", 2.0)
+    return d
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced by chi0_plan
+
+
+def _plan(d, eps=FAKE, ck=FAKE):
+    so = lib.load_library()
+    h = ctypes.c_void_p()
+    st = so.chi0_plan(ctypes.byref(h), ctypes.byref(d), eps, ck, None)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nk=(0, 4, 4)), -2),
+    (dict(n_bands=0), -2),
+    (dict(n_bands=65), -2),
+    (dict(band_lo=3, band_hi=2), -2),
+    (dict(band_lo=-1), -2),
+    (dict(band_hi=5), -2),
+    (dict(n_bands=40, band_lo=0, band_hi=40), -2),
+    (dict(n_orb=0), -2),
+    (dict(form=2), -1),
+    (dict(cma=3), -1),
+    (dict(mu=float("nan")), -3),
+    (dict(spin_factor=float("inf")), -3),
+    (dict(precision=1), -7),
+])
+def test_plan_rejects_bad_descriptors(kw, status):
+    st, h = _plan(_desc(**kw))
+    assert st == status
+    assert not h.value
+
+
+def test_plan_rejects_null_pointers():
+    assert _plan(_desc(), eps=None)[0] == -1
+    assert _plan(_desc(), ck=None)[0] == -1
+    assert _plan(_desc(cma=1), ck=None)[0] == 0
+
+
+def test_calls_validate_before_any_device_work():
+    so = lib.load_library()
+    st, h = _plan(_desc(nk=(3, 5, 2), n_bands=6, n_orb=6, band_lo=1, band_hi=5))
+    assert st == 0
+    try:
+        size = ctypes.c_size_t()
+        assert so.chi0_workspace_size(h, 3, 700, ctypes.byref(size)) == 0 and size.value > 0
+        assert so.chi0_workspace_size(h, 0, 1, ctypes.byref(size)) == -1
+        q = (lib._Q * 2)()
+        q[1].explicit_kq = 1                       # explicit without arrays
+        out = ctypes.c_void_p(0x2000)
+        ws = ctypes.c_void_p(0x3000)
+        assert so.chi0_static(h, 2, q, ws, 1 << 40, out) == -1
+        assert b"eps_kq" in so.chi0_last_error(h)
+        q[1].explicit_kq = 0
+        assert so.chi0_static(h, 0, q, ws, 1 << 40, out) == -1
+        assert so.chi0_static(h, 2, q, ws, 16, out) == -5          # workspace too small
+        assert so.chi0_static(h, 2, q, None, 1 << 40, out) == -5
+        assert so.chi0_dynamic(h, 2, q, 0, out, ws, 1 << 40, out) == -1
+        assert so.chi0_dynamic(h, 2, q, 4, None, ws, 1 << 40, out) == -1
+        assert so.chi0_dynamic(h, 2, q, 4, out, ws, 8, out) == -5
+        assert so.chi0_status_string(-5) == b"workspace too small"
+    finally:
+        so.chi0_destroy(h)
+    assert so.chi0_destroy(None) == 0
+
+
+def test_workspace_grows_with_frequencies_up_to_one_launch():
+    so = lib.load_library()
+    st, h = _plan(_desc(nk=(8, 8, 8), n_bands=4, n_orb=4))
+    try:
+        sizes = []
+        for nw in (1, 64, 512, 2048):
+            s = ctypes.c_size_t()
+            so.chi0_workspace_size(h, 1, nw, ctypes.byref(s))
+            sizes.append(s.value)
+        assert sizes[0] < sizes[1] < sizes[2] == sizes[3]
+    finally:
+        so.chi0_destroy(h)

@@ -1,0 +1,194 @@
+"""GPU parity: libchi0 (HIP, gfx950) against the CPU FP64 oracle on the same seeded inputs.
+
+Bar for the all-FP64 path: per q, max_w |chi_gpu - chi_oracle| / max_w |chi_oracle| <= 1e-10.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _plan(wl, **kw):
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    dev = torch.device("cuda:0")
+    eps = torch.from_numpy(np.ascontiguousarray(wl.eps_k)).to(dev)
+    ck = None if wl.c_k is None else torch.from_numpy(np.ascontiguousarray(wl.c_k)).to(dev)
+    lo, hi = wl.window()
+    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
+                        cma=wl.cma, form=kw.get("form", wl.form))
+    qs = []
+    for q in wl.qs:
+        if q.shift is not None:
+            qs.append(lib.Q(shift=q.shift))
+        else:
+            e = torch.from_numpy(np.ascontiguousarray(q.eps_kq)).to(dev)
+            c = None if (q.c_kq is None or wl.cma) else torch.from_numpy(np.ascontiguousarray(q.c_kq)).to(dev)
+            qs.append(lib.Q(eps_kq=e, c_kq=c))
+    return plan, qs
+
+
+def _relerr(got, ref):
+    return np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_matrix_elements_match_plain_contraction():
+    """K_A (FP64 MFMA) against |conj(C(k))^T C(k+q)|^2 computed with numpy."""
+    torch = _torch()
+    m = synth.tetragonal_two_site_model(2)
+    wl = synth.model_workload(m, (8, 8, 4), [np.array([0.13, 0.31, 0.07])], np.zeros(1), static=True)
+    wl.band_lo, wl.band_hi = 1, 9
+    plan, qs = _plan(wl)
+    _say("matrix elements 8x8x4, window [1,9)")
+    W = plan.matrix_elements(qs[0]).cpu().numpy()
+    ck = wl.c_k[:, :, 1:9]
+    ckq = wl.qs[0].c_kq[:, :, 1:9]
+    M = np.einsum("kon,kom->nmk", ck.conj(), ckq)
+    ref = np.abs(M) ** 2
+    assert np.max(np.abs(W - ref)) < 1e-13
+
+
+def test_matrix_elements_shift_mode_and_wide_window():
+    """Commensurate shift, 20 orbitals / 20 bands (two 16-wide band tiles, 5 orbital steps)."""
+    torch = _torch()
+    m = synth.random_model("tetragonal", 9, 20)
+    wl = synth.model_workload(m, (4, 4, 3), None, np.zeros(1), shifts=[(1, 3, 2)], static=True)
+    plan, qs = _plan(wl)
+    _say("matrix elements shift mode 20 bands")
+    W = plan.matrix_elements(qs[0]).cpu().numpy()
+    n = wl.nk
+    idx = np.arange(wl.n_k).reshape(n)
+    kq = np.roll(idx, shift=(-1, -3, -2), axis=(0, 1, 2)).ravel()
+    M = np.einsum("kon,kom->nmk", wl.c_k.conj(), wl.c_k[kq])
+    assert np.max(np.abs(W - np.abs(M) ** 2)) < 1e-13
+
+
+def test_static_sc_cma_full_config():
+    """Single-band SC model, CMA, 16^3 mesh, all 8 q (7 mesh shifts + 1 explicit)."""
+    wl = synth.make_workload("sc_cma")
+    plan, qs = _plan(wl)
+    _say("static sc_cma 16^3, 8 q")
+    got = plan.static(qs).cpu().numpy()
+    ref = np.array([oracle.chi0(wl, i)[0].real for i in range(len(wl.qs))])
+    for i in range(len(ref)):
+        assert abs(got[i] - ref[i]) <= TOL * abs(ref[i]), (i, got[i], ref[i])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_static_tetragonal_matrix_elements(form):
+    """10-orbital two-site model, all 100 band pairs, explicit k+q, ragged mesh 12x10x3."""
+    wl = synth.make_workload("tetra_static", nk=(12, 10, 3), nq=16, q_subset=[0, 5, 11, 15])
+    wl.form = form
+    plan, qs = _plan(wl)
+    _say("static tetragonal 12x10x3 form", form)
+    got = plan.static(qs).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i)[0].real
+        assert abs(got[i] - ref) <= TOL * abs(ref), (i, got[i], ref)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_dynamic_tetragonal(form):
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", nk=(8, 8, 3), nq=8, q_subset=[1, 6], nw=80)
+    wl.form = form
+    om = np.concatenate([wl.omega, [-0.7, -0.05, 3.5, 25.0]])
+    plan, qs = _plan(wl)
+    _say("dynamic tetragonal 8x8x3 form", form, "nw", len(om))
+    got = plan.dynamic(qs, torch.from_numpy(om).cuda()).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i, omega=om)
+        assert _relerr(got[i], ref) <= TOL, (i, _relerr(got[i], ref))
+
+
+def test_dynamic_bcc_band_window():
+    """9-orbital bcc model with a 7-band window (band truncation), explicit k+q."""
+    torch = _torch()
+    wl = synth.make_workload("bcc_dynamic", nk=(6, 6, 6), nq=8, q_subset=[2, 5], nw=64, n_keep=7)
+    plan, qs = _plan(wl)
+    _say("dynamic bcc 6^3 window", wl.window())
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i)
+        assert _relerr(got[i], ref) <= TOL
+
+
+def test_dynamic_more_than_512_frequencies_and_shift_mode():
+    """nw = 600 (two frequency launches), commensurate shift, 3-orbital model."""
+    torch = _torch()
+    m = synth.random_model("sc", 4, 3)
+    wl = synth.model_workload(m, (5, 4, 3), None, np.linspace(-1.0, 3.0, 600), shifts=[(2, 1, 1)])
+    plan, qs = _plan(wl)
+    _say("dynamic 600 omega shift mode")
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    ref = oracle.chi0(wl, 0)
+    assert _relerr(got[0], ref) <= TOL
+
+
+def test_static_equals_dynamic_at_zero_and_determinism():
+    torch = _torch()
+    wl = synth.make_workload("tetra_static", nk=(8, 8, 2), nq=8, q_subset=[3])
+    plan, qs = _plan(wl)
+    _say("static vs dynamic at w=0, determinism")
+    s1 = plan.static(qs).cpu().numpy()
+    s2 = plan.static(qs).cpu().numpy()
+    assert np.array_equal(s1, s2)
+    om = torch.tensor([0.0, 0.5], dtype=torch.float64, device="cuda")
+    d1 = plan.dynamic(qs, om).cpu().numpy()
+    d2 = plan.dynamic(qs, om).cpu().numpy()
+    assert np.array_equal(d1, d2)
+    assert abs(d1[0, 0].real - s1[0]) <= 1e-13 * abs(s1[0])
+    assert abs(d1[0, 0].imag) <= 1e-13 * abs(s1[0])
+
+
+def test_fully_occupied_window_gives_zero():
+    """A window of bands that are all below mu everywhere has no carved region: chi0 == 0."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_static", nk=(4, 4, 2), nq=8, q_subset=[2])
+    assert wl.eps_k[:3].max() < wl.mu - 0.01 and wl.qs[0].eps_kq[:3].max() < wl.mu - 0.01
+    wl.band_lo, wl.band_hi = 0, 3
+    plan, qs = _plan(wl)
+    assert plan.static(qs).cpu().numpy()[0] == 0.0
+
+
+def test_full_size_dynamic_sampled_outputs():
+    """The benchmark's configuration (10-orbital model, 64x64x8 mesh, 512 w, batch launch) on
+    2 of its 64 q; the oracle checks 3 sampled frequencies of each."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", q_subset=[7, 40], workers=8)
+    plan, qs = _plan(wl)
+    _say("full-size dynamic 64x64x8, 2 q x 512 w")
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    for i, sample in enumerate([[5, 200, 470], [64, 333, 511]]):
+        ref = oracle.chi0(wl, i, omega=wl.omega[sample])
+        assert _relerr(got[i][sample], ref) <= TOL, (i, got[i][sample], ref)
+
+
+def test_full_size_static_sampled_q():
+    """Static chi0 of the 10-orbital model on the full 64x64x8 mesh, 2 of its 256 q."""
+    wl = synth.make_workload("tetra_static", q_subset=[31, 200], workers=8)
+    plan, qs = _plan(wl)
+    _say("full-size static 64x64x8, 2 q")
+    got = plan.static(qs).cpu().numpy()
+    for i in range(2):
+        ref = oracle.chi0(wl, i)[0].real
+        assert abs(got[i] - ref) <= TOL * abs(ref), (i, got[i], ref)

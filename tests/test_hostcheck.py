@@ -1,0 +1,127 @@
+"""CPU checks of the GPU path's per-tetrahedron arithmetic against the oracle.
+
+``paper_1407_3444_amd/csrc/chi0_math.h`` (carving and the far-series /
+near-branch weight evaluation the kernels use) is compiled for the host here
+and compared with the oracle's independent carving and divided differences on
+random and adversarial tetrahedra.  This runs without a GPU.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hostcheck", "chi0_hostcheck.cpp")
+LIB = os.path.join(HERE, "hostcheck", "libchi0_hostcheck.so")
+
+
+@pytest.fixture(scope="module")
+def hc():
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", SRC, "-o", tmp])
+    os.replace(tmp, LIB)
+    lib = ctypes.CDLL(LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.hc_weight_sum.argtypes = [dp, dp, ctypes.c_double, dp]
+    lib.hc_unit.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
+    lib.hc_unit.restype = ctypes.c_int
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _weight_sum(hc, D, W, w):
+    D = np.ascontiguousarray(D, float)
+    W = np.ascontiguousarray(W, float)
+    out = np.zeros(2)
+    hc.hc_weight_sum(_p(D), _p(W), float(w), _p(out))
+    return complex(out[0], out[1])
+
+
+def _cases():
+    rng = np.random.default_rng(17)
+    out = []
+    for _ in range(300):
+        out.append((rng.uniform(0, 2, 4), rng.uniform(0, 1, 4), rng.uniform(-1, 3)))
+    for _ in range(200):   # clustered, far and near
+        c = rng.uniform(0.2, 1.8)
+        out.append((c + rng.uniform(0, 1, 4) * 10 ** rng.uniform(-8, -1), rng.uniform(0, 1, 4),
+                    c + rng.choice([-1, 1]) * 10 ** rng.uniform(-3, 0.5)))
+    for _ in range(100):   # ties and near ties
+        y = rng.uniform(0, 2, 4)
+        y[1] = y[0] + (0.0 if rng.random() < 0.5 else 10 ** rng.uniform(-13, -5))
+        if rng.random() < 0.3:
+            y[3] = y[2]
+        out.append((y, rng.uniform(0, 1, 4), rng.uniform(-1, 3)))
+    for _ in range(100):   # w close to or at a node
+        y = rng.uniform(0, 2, 4)
+        j = rng.integers(4)
+        w = y[j] if rng.random() < 0.3 else y[j] + rng.choice([-1, 1]) * 10 ** rng.uniform(-12, -2)
+        out.append((y, rng.uniform(0, 1, 4), w))
+    return out
+
+
+def test_weight_sum_matches_oracle(hc):
+    worst = 0.0
+    for D, W, w in _cases():
+        ref = np.dot(W, oracle.weights(D, w))
+        got = _weight_sum(hc, D, W, w)
+        scale = np.sum(np.abs(W) * np.abs(oracle.weights(D, w)))
+        err = abs(got - ref) / scale
+        worst = max(worst, err)
+        assert err < 5e-12, (D, W, w, got, ref)
+    print("worst relative error", worst)
+
+
+def test_static_weight_sum_matches_oracle(hc):
+    """w = 0 with nodes on both sides, at zero and near zero (the static kernel's cases)."""
+    rng = np.random.default_rng(23)
+    for _ in range(400):
+        D = rng.uniform(0, 1.5, 4) * (10 ** rng.uniform(-4, 0))
+        if rng.random() < 0.3:
+            D[rng.integers(4)] = 0.0
+        W = rng.uniform(0, 1, 4)
+        ref = np.dot(W, oracle.weights(D, 0.0))
+        got = _weight_sum(hc, D, W, 0.0)
+        scale = np.sum(np.abs(W) * np.abs(oracle.weights(D, 0.0)))
+        assert abs(got - ref) < 5e-12 * scale
+
+
+def _oracle_unit(a, b, Wc, w, form):
+    """contribution of one (tetrahedron, band pair) from the oracle's carving and weights"""
+    D = b - a
+    tot = 0j
+    regions = [(1, 1.0)] if form == 1 else [(1, 1.0), (2, -1.0)]
+    for region, sign in regions:
+        verts, vols = oracle.carve(a, b, region)
+        for V, v in zip(verts, vols):
+            if v == 0.0:
+                continue
+            Dv, Wv = V @ D, V @ Wc
+            tot += sign * v * np.dot(Wv, oracle.weights(Dv, w))
+            if form == 1:
+                tot -= sign * v * np.dot(Wv, oracle.weights(-Dv, w))
+    return tot
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_carved_unit_matches_oracle(hc, form):
+    rng = np.random.default_rng(31 + form)
+    for it in range(400):
+        a = rng.normal(size=4)
+        b = rng.normal(size=4) + (0.5 if it % 3 == 0 else 0.0)
+        if it % 7 == 0:
+            a[rng.integers(4)] = 0.0
+        Wc = rng.uniform(0, 1, 4)
+        w = 0.0 if it % 2 == 0 else rng.uniform(-2, 3)
+        ref = _oracle_unit(a, b, Wc, w, form)
+        out = np.zeros(2)
+        hc.hc_unit(_p(a), _p(b), _p(Wc), float(w), form, _p(out))
+        got = complex(out[0], out[1])
+        assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (it, a, b, w, got, ref)
