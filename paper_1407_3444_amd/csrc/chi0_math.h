@@ -38,10 +38,16 @@
 namespace chi0 {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kFarTerms = 24;          // series terms kept in the far branch
-constexpr double kRhoFar = 0.2;        // far branch when half-span <= kRhoFar * |w - c|
-constexpr double kThetaEntry = 0.25;   // Taylor sub-entry when span <= kThetaEntry * |w - x_end|
-constexpr int kTaylorMaxTerms = 48;
+#ifndef CHI0_FAR_TERMS
+#define CHI0_FAR_TERMS 40
+#define CHI0_RHO_FAR 0.4
+#endif
+#ifndef CHI0_THETA_ENTRY
+#define CHI0_THETA_ENTRY 0.1
+#endif
+constexpr int kFarTerms = CHI0_FAR_TERMS;          // series terms kept in the far branch
+constexpr double kRhoFar = CHI0_RHO_FAR;           // far branch when half-span <= kRhoFar * |w - c|
+constexpr double kThetaEntry = CHI0_THETA_ENTRY;   // series sub-entry when span <= kThetaEntry * |w - x_end|
 
 struct cplx {
     double re, im;
@@ -194,6 +200,7 @@ C0_HD void far_coeffs(const double y[4], const double w[4], double c, double *a)
     double z0 = y[0] - c, z1 = y[1] - c, z2 = y[2] - c, z3 = y[3] - c;
     double P0 = 1.0, P1 = 1.0, P2 = 1.0, P3 = 1.0;      // H_{m-1} over growing variable sets
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;      // their W-derivatives
+#pragma unroll
     for (int m = 1; m <= kFarTerms; ++m) {
         double n0 = z0 * P0;
         double e0 = fma(w[0], P0, z0 * d0);
@@ -229,100 +236,119 @@ C0_HD cplx hder_low(int n, double u, cplx L)
     }
 }
 
-// Value and W-derivative of the divided difference h[y_i..y_j] (p = j - i) as a
-// Taylor series about the node y_k (k = i or j): sum_m h^(p+m)(y_k)/(p+m)! H_m(y - y_k).
-C0_HD void taylor_entry(const double *y, const double *w, int i, int j, int k, double om, cplx Lk,
-                        cplx &val, cplx &tan)
+// Value and W-derivative of the divided difference h[y_i..y_{i+P}] as a Taylor series of
+// kEntryTerms terms about the node c (one of its two end nodes), with u = w - c, L = Log(u):
+//   sum_m h^(P+m)(c)/(P+m)! H_m(y - c),  H_m of the offsets scaled by 1/u.
+// Exact to rounding when the span is at most kThetaEntry * |u|; computed for every lane
+// (no data-dependent trip count) and selected by the caller.
+constexpr int kEntryTerms = 18;
+
+template <int P>
+C0_HD void taylor_fixed(const double *y, const double *w, double c, double u, cplx L, cplx &val, cplx &tan)
 {
-    const int p = j - i;
-    const double u = om - y[k];
     const double inv = 1.0 / u;
-    double z[4], dz[4];
-    double rho = 0.0;
-    for (int v = 0; v <= p; ++v) {
-        z[v] = (y[i + v] - y[k]) * inv;      // offsets in units of u
-        dz[v] = w[i + v] * inv;
-        rho = fmax(rho, fabs(z[v]));
+    double z[P + 1], dz[P + 1], Hp[P + 1], dHp[P + 1];
+#pragma unroll
+    for (int v = 0; v <= P; ++v) {
+        z[v] = (y[v] - c) * inv;
+        dz[v] = w[v] * inv;
+        Hp[v] = 1.0;
+        dHp[v] = 0.0;
     }
-    // H_m(z) and its derivative, over the growing variable set, term by term
-    double P[4], dP[4];
-    for (int v = 0; v <= p; ++v) { P[v] = 1.0; dP[v] = 0.0; }
-    const double up = (p == 4) ? inv : (p == 3 ? 1.0 : (p == 2 ? u : u * u));   // u^(3-p), p in 1..3
-    double um = 1.0;                        // u^m for the low-order (logarithmic) terms
+    const double up = (P == 1) ? u * u : u;      // u^(3-P)
     val = cmk(0.0, 0.0);
     tan = cmk(0.0, 0.0);
-    double bound = 1.0;                     // C(m+p, p) rho^m
-    for (int m = 0; m < kTaylorMaxTerms; ++m) {
+    double um = 1.0;
+#pragma unroll
+    for (int m = 0; m < kEntryTerms; ++m) {
         double H = 1.0, dH = 0.0;
         if (m > 0) {
             double prev = 0.0, dprev = 0.0;
-            for (int v = 0; v <= p; ++v) {
-                const double nP = fma(z[v], P[v], prev);
-                const double ndP = fma(dz[v], P[v], fma(z[v], dP[v], dprev));
-                P[v] = nP; dP[v] = ndP;
-                prev = nP; dprev = ndP;
+#pragma unroll
+            for (int v = 0; v <= P; ++v) {
+                const double nP = fma(z[v], Hp[v], prev);
+                const double ndP = fma(dz[v], Hp[v], fma(z[v], dHp[v], dprev));
+                Hp[v] = nP;
+                dHp[v] = ndP;
+                prev = nP;
+                dprev = ndP;
             }
-            H = prev; dH = dprev;
+            H = prev;
+            dH = dprev;
         }
-        const int n = p + m;
+        const int n = P + m;
         if (n >= 4) {
             const double nn = (double)n;
             const double cf = 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0)) * up;
             val.re = fma(cf, H, val.re);
             tan.re = fma(cf, dH, tan.re);
         } else {
-            const cplx hd = hder_low(n, u, Lk);
+            const cplx hd = hder_low(n, u, L);
             val = cfma(val, hd, um * H);
             tan = cfma(tan, hd, um * dH);
             um *= u;
         }
-        bound *= (double)(m + p + 1) / (double)(m + 1) * rho;
-        if (m >= 4 && bound < 1e-17) break;
     }
 }
 
-// Near branch: sum_j W_j J_j at frequency om for sorted nodes y with weights w.
+C0_HD cplx csel(bool c, cplx a, cplx b) { return cmk(c ? a.re : b.re, c ? a.im : b.im); }
+
+// One Newton entry from its two children, or (when its nodes cluster within kThetaEntry of
+// their distance to w) from the Taylor series about its farther end node.
+template <int P>
+C0_HD void newton_entry(const double *y, const double *w, const double *u, const cplx *L, cplx A, cplx dA,
+                        cplx B, cplx dB, cplx &V, cplx &T)
+{
+    // recursion: (A - B) / (y_P - y_0), A = [y_1..y_P], B = [y_0..y_{P-1}]
+    const double span = y[P] - y[0];
+    const double inv = 1.0 / span;
+    const cplx E = cscale(csub(A, B), inv);
+    const double dspan = (w[P] - w[0]) * inv;
+    cplx dE = cscale(csub(dA, dB), inv);
+    dE = cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
+    // series about the end node farther from w
+    const double d0 = fabs(u[0]), dP = fabs(u[P]);
+    const bool first = d0 >= dP;
+    const double far = first ? d0 : dP;
+    const double uc = first ? u[0] : u[P];
+    const cplx Lc = csel(first, L[0], L[P]);
+    const bool use_series = span <= kThetaEntry * far;
+    const bool at_w = far == 0.0;                 // every node at w: h[..] and its derivative vanish
+    cplx Vt, Tt;
+    taylor_fixed<P>(y, w, first ? y[0] : y[P], at_w ? 1.0 : uc, Lc, Vt, Tt);
+    if (at_w) { Vt = cmk(0.0, 0.0); Tt = cmk(0.0, 0.0); }
+    V = csel(use_series, Vt, E);
+    T = csel(use_series, Tt, dE);
+}
+
+// Near branch: sum_j W_j J_j at frequency om for sorted nodes y with weights w, as the
+// W-derivative of the Newton table of h over the 4 nodes (leaves from 4 logarithms).
 C0_HD cplx near_eval(const double y[4], const double w[4], double om)
 {
-    cplx V[4][4], T[4][4];            // value / W-derivative of h[y_i..y_j], i <= j
-    cplx L[4];
     double u[4];
+    cplx L[4], V0[4], T0[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         u[i] = om - y[i];
-        if (u[i] == 0.0) {            // h and h' vanish at u = 0
-            L[i] = cmk(0.0, 0.0);
-            V[i][i] = cmk(0.0, 0.0);
-            T[i][i] = cmk(0.0, 0.0);
-        } else {
-            L[i] = cmk(log(fabs(u[i])), u[i] < 0.0 ? kPi : 0.0);
-            V[i][i] = hder_low(0, u[i], L[i]);
-            T[i][i] = cscale(hder_low(1, u[i], L[i]), w[i]);
-        }
+        const bool zero = u[i] == 0.0;             // h and h' vanish at u = 0
+        L[i] = cmk(zero ? 0.0 : log(fabs(u[i])), u[i] < 0.0 ? kPi : 0.0);
+        V0[i] = hder_low(0, u[i], L[i]);
+        T0[i] = cscale(hder_low(1, u[i], L[i]), w[i]);
     }
+    cplx V1[3], T1[3];
 #pragma unroll
-    for (int p = 1; p < 4; ++p) {
+    for (int i = 0; i < 3; ++i)
+        newton_entry<1>(y + i, w + i, u + i, L + i, V0[i + 1], T0[i + 1], V0[i], T0[i], V1[i], T1[i]);
+    cplx V2[2], T2[2];
 #pragma unroll
-        for (int i = 0; i + p < 4; ++i) {
-            const int j = i + p;
-            const double span = y[j] - y[i];
-            const double di = fabs(u[i]), dj = fabs(u[j]);
-            const double far = fmax(di, dj);
-            if (span <= kThetaEntry * far) {
-                const int k = di >= dj ? i : j;
-                taylor_entry(y, w, i, j, k, om, k == i ? L[i] : L[j], V[i][j], T[i][j]);
-            } else {
-                const double inv = 1.0 / span;
-                const cplx E = cscale(csub(V[i + 1][j], V[i][j - 1]), inv);
-                const double dspan = (w[j] - w[i]) * inv;
-                cplx dE = cscale(csub(T[i + 1][j], T[i][j - 1]), inv);
-                dE = cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
-                V[i][j] = E;
-                T[i][j] = dE;
-            }
-        }
-    }
-    return T[0][3];
+    for (int i = 0; i < 2; ++i)
+        newton_entry<2>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i]);
+    // the top entry spans all nodes; in the near branch its span exceeds its distance to w
+    const double inv = 1.0 / (y[3] - y[0]);
+    const cplx E = cscale(csub(V2[1], V2[0]), inv);
+    const double dspan = (w[3] - w[0]) * inv;
+    cplx dE = cscale(csub(T2[1], T2[0]), inv);
+    return cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
 }
 
 // sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.

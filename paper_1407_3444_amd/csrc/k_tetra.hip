@@ -26,13 +26,13 @@ namespace chi0 {
 
 namespace {
 
-constexpr int kCapDyn = 64;     // final tetrahedra per LDS list (dynamic)
+constexpr int kCapDyn = 32;     // final tetrahedra per LDS list (dynamic)
 constexpr int kCapStat = 192;   // final tetrahedra per LDS list (static)
+constexpr int kQCap = 16;       // near-branch work items queued per lane
 
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W at the same corners
-    double c, r;                // centre and half-span of the D range
     double a[kFarTerms];        // far-branch series coefficients
 };
 
@@ -181,9 +181,11 @@ __device__ __forceinline__ int wave_inclusive_scan(int x, int lane)
 
 // Fill the LDS list with the final tetrahedra of lanes [start, next) of this round.
 // Returns the number of records; next_out receives the first lane left for a later pass.
+// The unit's corner values are loaded again here (cache hits) rather than kept in
+// registers across the evaluation of the list.
 template <class Rec, int CAP>
-__device__ __forceinline__ int fill_list(const Vtx t[4], bool valid, int cnt, int start, int lane,
-                                         int form, Rec *list, int &next_out)
+__device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, int64_t u, bool valid, int cnt,
+                                         int start, int lane, Rec *list, int &next_out)
 {
     const int c = (lane >= start) ? cnt : 0;
     const int incl = wave_inclusive_scan(c, lane);
@@ -192,9 +194,82 @@ __device__ __forceinline__ int fill_list(const Vtx t[4], bool valid, int cnt, in
     const unsigned long long mask = __ballot(fits);
     const int next = start + __popcll(mask);
     const int nrec = __shfl(incl, next - 1, kWave);
-    if (fits && valid && cnt > 0) write_unit<Rec>(t, form, list, excl, incl);
+    if (fits && valid && cnt > 0) {
+        Vtx t[4];
+        load_unit(M, Q, u, t);
+        write_unit<Rec>(t, M.form, list, excl, incl);
+    }
     next_out = next;
     return nrec;
+}
+
+__device__ __forceinline__ double uniform(double x)
+{
+    // a wave-uniform value moved to scalar registers
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// 1/d to full FP64 precision: hardware reciprocal estimate + two Newton steps
+__device__ __forceinline__ double recip(double d)
+{
+    double t = __builtin_amdgcn_rcp(d);
+    t = fma(t, fma(-d, t, 1.0), t);
+    t = fma(t, fma(-d, t, 1.0), t);
+    return t;
+}
+
+template <int K>
+__device__ __forceinline__ double horner(const double *a, double t)
+{
+    double s = a[K - 1];
+#pragma unroll
+    for (int m = K - 2; m >= 0; --m) s = fma(s, t, a[m]);
+    return s * t;
+}
+
+__device__ __forceinline__ double wave_min(double x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmin(x, __shfl_xor(x, d, kWave));
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, kWave));
+    return x;
+}
+
+// Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.
+// Lanes with an empty queue idle; the loop ends when every queue is empty.
+template <int NSLOT>
+__device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
+                                           const double *om, cplx *acc)
+{
+    while (__any(qn > 0)) {
+        if (qn > 0) {
+            --qn;
+            const int e = queue[qn][lane];
+            const int r = e >> 3, s = e & 7;
+            double y[4], w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
+            double o = om[0];
+#pragma unroll
+            for (int ss = 1; ss < NSLOT; ++ss) o = (s == ss) ? om[ss] : o;
+            const cplx z = near_eval(y, w, o);
+#pragma unroll
+            for (int ss = 0; ss < NSLOT; ++ss) {
+                const bool hit = s == ss;
+                acc[ss].re += hit ? z.re : 0.0;
+                acc[ss].im += hit ? z.im : 0.0;
+            }
+        }
+    }
 }
 
 template <int NSLOT>
@@ -203,6 +278,7 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
                                                            double *__restrict__ partial)
 {
     __shared__ DynRec list[kCapDyn];
+    __shared__ uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
     const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
@@ -211,28 +287,32 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
     const int64_t u0 = (int64_t)blk * upb;
     const int64_t u1 = min(u0 + upb, n_units);
 
+    // frequencies of this lane (slot s holds w[lane + 64 s]) and each slot's range over the wave
     double om[NSLOT];
+    bool live[NSLOT];
     cplx acc[NSLOT];
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
         const int idx = lane + kWave * s;
-        om[s] = omega[idx < nw ? idx : nw - 1];
+        live[s] = idx < nw;
+        om[s] = omega[live[s] ? idx : nw - 1];
         acc[s] = cmk(0.0, 0.0);
     }
+    int qn = 0;
 
     for (int64_t base = u0; base < u1; base += kWave) {
         const int64_t u = base + lane;
         const bool valid = u < u1;
-        Vtx t[4];
         int cnt = 0;
         if (valid) {
+            Vtx t[4];
             load_unit(M, Q, u, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<DynRec, kCapDyn>(t, valid, cnt, start, lane, M.form, list, next);
+            const int nrec = fill_list<DynRec, kCapDyn>(M, Q, u, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -241,34 +321,43 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
                 double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
                 double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
                 sort4(y, w);
-                const double c = 0.5 * (y[0] + y[3]);
-                double a[kFarTerms];
-                far_coeffs(y, w, c, a);
+                far_coeffs(y, w, 0.5 * (y[0] + y[3]), list[r].a);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
-                list[r].c = c;
-                list[r].r = 0.5 * (y[3] - y[0]);
-#pragma unroll
-                for (int k = 0; k < kFarTerms; ++k) list[r].a[k] = a[k];
             }
             __syncthreads();
             for (int r = 0; r < nrec; ++r) {
-                double y[4], w[4], a[kFarTerms];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
-                const double c = list[r].c, hs = list[r].r;
-#pragma unroll
-                for (int k = 0; k < kFarTerms; ++k) a[k] = list[r].a[k];
+                // all slots at once: 8 independent Horner chains in the far series, each
+                // coefficient read once from LDS (a broadcast) and used by every slot
+                const double y0 = list[r].y[0], y3 = list[r].y[3];
+                const double c = 0.5 * (y0 + y3), hs = 0.5 * (y3 - y0);
+                double tt[NSLOT], f[NSLOT];
+                bool nearb[NSLOT];
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s) {
                     const double d = om[s] - c;
-                    if (hs <= kRhoFar * fabs(d)) {
-                        acc[s].re += far_horner(a, 1.0 / d);
-                    } else {
-                        acc[s] = cadd(acc[s], near_eval(y, w, om[s]));
+                    nearb[s] = !(hs <= kRhoFar * fabs(d));
+                    tt[s] = recip(nearb[s] ? 1.0 : d);
+                    f[s] = list[r].a[kFarTerms - 1];
+                }
+#pragma unroll
+                for (int m = kFarTerms - 2; m >= 0; --m) {
+                    const double am = list[r].a[m];
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], am);
+                }
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) {
+                    if (!nearb[s]) {
+                        acc[s].re = fma(f[s], tt[s], acc[s].re);
+                    } else if (live[s]) {
+                        queue[qn][lane] = (uint16_t)((r << 3) | s);
+                        ++qn;
                     }
                 }
+                if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, om, acc);
             }
+            drain_near<NSLOT>(list, queue, qn, lane, om, acc);
             __syncthreads();
         }
     }
@@ -298,16 +387,16 @@ __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B,
     for (int64_t base = u0; base < u1; base += kWave) {
         const int64_t u = base + lane;
         const bool valid = u < u1;
-        Vtx t[4];
         int cnt = 0;
         if (valid) {
+            Vtx t[4];
             load_unit(M, Q, u, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<StatRec, kCapStat>(t, valid, cnt, start, lane, M.form, list, next);
+            const int nrec = fill_list<StatRec, kCapStat>(M, Q, u, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
