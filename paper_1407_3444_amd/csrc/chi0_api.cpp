@@ -59,19 +59,11 @@ int64_t n_units(const chi0_plan_s *p)
     return 6 * p->mesh.nk * (int64_t)p->mesh.nbw * p->mesh.nbw;
 }
 
-// Units per workgroup: about 1024 workgroups per q, at least 4 rounds of 64.
-int64_t units_per_block(const chi0_plan_s *p)
-{
-    const int64_t u = n_units(p);
-    int64_t upb = (u + 1023) / 1024;
-    upb = (upb + kWave - 1) / kWave * kWave;
-    return std::max<int64_t>(upb, 4 * kWave);
-}
-
+// Workgroups per q: up to 1024, each taking at least 4 rounds of 64 units.
 int n_blocks(const chi0_plan_s *p)
 {
-    const int64_t upb = units_per_block(p);
-    return (int)((n_units(p) + upb - 1) / upb);
+    const int64_t rounds = (n_units(p) + kWave - 1) / kWave;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rounds + 3) / 4));
 }
 
 struct Layout {
@@ -293,7 +285,6 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
     chi0_workspace_size(p, nq, 1, &need);
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     const int nblk = n_blocks(p);
-    const int64_t upb = units_per_block(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
@@ -304,7 +295,7 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
         if (!p->d.cma &&
             (e = timed(p, 0, [&] { return launch_contract_f64(p->mesh, B, nqb, p->stream); })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
-        if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, nqb, upb, nblk, partial, p->stream); })) !=
+        if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, nqb, nblk, partial, p->stream); })) !=
             hipSuccess)
             return device_fail(p, e, "tetrahedron kernel");
         if ((e = timed(p, 2, [&] { return launch_reduce(partial, nqb, nblk, 1, scale, chi + q0, 1, p->stream); })) !=
@@ -327,7 +318,6 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
     chi0_workspace_size(p, nq, nw, &need);
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     const int nblk = n_blocks(p);
-    const int64_t upb = units_per_block(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
@@ -341,7 +331,7 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
             if ((e = timed(p, 1, [&] {
-                     return launch_tetra_dynamic(p->mesh, B, nqb, upb, nblk, omega + w0, nwc, partial, p->stream);
+                     return launch_tetra_dynamic(p->mesh, B, nqb, nblk, omega + w0, nwc, partial, p->stream);
                  })) != hipSuccess)
                 return device_fail(p, e, "tetrahedron kernel");
             if ((e = timed(p, 2, [&] {

@@ -39,13 +39,12 @@ struct MeshDev {
 hipError_t launch_contract_f64(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s);
 
 // K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
-hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq,
-                               int64_t units_per_block, int nblocks, double *partial, hipStream_t s);
+hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
+                               hipStream_t s);
 
 // K_B dynamic: per-block partial sums into partial[nq][nblocks][nw][2], nw <= kMaxOmegaPerLaunch.
-hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq,
-                                int64_t units_per_block, int nblocks, const double *omega, int nw,
-                                double *partial, hipStream_t s);
+hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
+                                const double *omega, int nw, double *partial, hipStream_t s);
 
 // Census of the work of a dynamic call: counts[0..3] += active units, final tetrahedra,
 // near-branch and far-branch (final tetrahedron, frequency) evaluations.

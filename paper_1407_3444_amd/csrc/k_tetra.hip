@@ -1,8 +1,10 @@
 // k_tetra.hip -- the tetrahedron kernel of the chi0 path (K_B).
 //
 // One work unit is one (mesh tetrahedron, band pair) of one q.  A workgroup is
-// one 64-lane wave that owns a contiguous range of units.  Each round, every
-// lane takes one unit, loads the 4 corner values of e = eps_n(k),
+// one 64-lane wave; rounds of 64 consecutive units are dealt to the workgroups
+// round-robin, so every workgroup sees the same mix of band pairs (the work of
+// a pair depends strongly on where its bands lie relative to mu).  Each round,
+// every lane takes one unit, loads the 4 corner values of e = eps_n(k),
 // e' = eps_m(k+q) and W_nm(k) (coalesced: consecutive lanes hold consecutive
 // cells), carves it into final tetrahedra -- first by e = mu, then by
 // e' = mu (Sec. II) -- and appends them to a list in LDS at an offset from a
@@ -28,12 +30,12 @@ namespace {
 
 constexpr int kCapDyn = 32;     // final tetrahedra per LDS list (dynamic)
 constexpr int kCapStat = 192;   // final tetrahedra per LDS list (static)
-constexpr int kQCap = 16;       // near-branch work items queued per lane
+constexpr int kQCap = 48;       // near-branch work items queued per lane
 
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W at the same corners
-    double a[kFarTerms];        // far-branch series coefficients
+    alignas(16) double a[kFarTerms];   // far-branch series coefficients
 };
 
 struct StatRec {
@@ -42,15 +44,6 @@ struct StatRec {
 };
 
 constexpr int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-
-__device__ __forceinline__ int xcd_remap(int b, int nblocks)
-{
-    // hardware dispatches block b to XCD b % 8; give each XCD a contiguous run of
-    // logical blocks so neighbouring cells share that XCD's L2
-    const int per = nblocks / 8, rem = nblocks % 8;
-    const int x = b % 8, j = b / 8;
-    return x * per + min(x, rem) + j;
-}
 
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 
@@ -273,7 +266,7 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
 }
 
 template <int NSLOT>
-__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int64_t upb, int nblocks,
+__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
                                                            const double *__restrict__ omega, int nw,
                                                            double *__restrict__ partial)
 {
@@ -282,10 +275,8 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
     const int qi = blockIdx.y;
     const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
-    const int blk = xcd_remap(blockIdx.x, nblocks);
+    const int blk = blockIdx.x;
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
-    const int64_t u0 = (int64_t)blk * upb;
-    const int64_t u1 = min(u0 + upb, n_units);
 
     // frequencies of this lane (slot s holds w[lane + 64 s]) and each slot's range over the wave
     double om[NSLOT];
@@ -300,9 +291,11 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
     }
     int qn = 0;
 
-    for (int64_t base = u0; base < u1; base += kWave) {
+    // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
+    // samples all band pairs, so the work per workgroup is even
+    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
         const int64_t u = base + lane;
-        const bool valid = u < u1;
+        const bool valid = u < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
@@ -327,10 +320,17 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
             }
             __syncthreads();
             for (int r = 0; r < nrec; ++r) {
-                // all slots at once: 8 independent Horner chains in the far series, each
-                // coefficient read once from LDS (a broadcast) and used by every slot
+                // all slots at once: 8 independent Horner chains in the far series; the
+                // coefficients are read from LDS (broadcast) into registers in one burst
                 const double y0 = list[r].y[0], y3 = list[r].y[3];
                 const double c = 0.5 * (y0 + y3), hs = 0.5 * (y3 - y0);
+                double a[kFarTerms];
+#pragma unroll
+                for (int m = 0; m < kFarTerms; m += 2) {
+                    const double2 v = *reinterpret_cast<const double2 *>(&list[r].a[m]);
+                    a[m] = v.x;
+                    a[m + 1] = v.y;
+                }
                 double tt[NSLOT], f[NSLOT];
                 bool nearb[NSLOT];
 #pragma unroll
@@ -338,13 +338,12 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
                     const double d = om[s] - c;
                     nearb[s] = !(hs <= kRhoFar * fabs(d));
                     tt[s] = recip(nearb[s] ? 1.0 : d);
-                    f[s] = list[r].a[kFarTerms - 1];
+                    f[s] = a[kFarTerms - 1];
                 }
 #pragma unroll
                 for (int m = kFarTerms - 2; m >= 0; --m) {
-                    const double am = list[r].a[m];
 #pragma unroll
-                    for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], am);
+                    for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], a[m]);
                 }
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s) {
@@ -372,21 +371,19 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
     }
 }
 
-__global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int64_t upb, int nblocks,
+__global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int nblocks,
                                                           double *__restrict__ partial)
 {
     __shared__ StatRec list[kCapStat];
     const int qi = blockIdx.y;
     const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
-    const int blk = xcd_remap(blockIdx.x, nblocks);
+    const int blk = blockIdx.x;
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
-    const int64_t u0 = (int64_t)blk * upb;
-    const int64_t u1 = min(u0 + upb, n_units);
     double acc = 0.0;
-    for (int64_t base = u0; base < u1; base += kWave) {
+    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
         const int64_t u = base + lane;
-        const bool valid = u < u1;
+        const bool valid = u < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
@@ -469,8 +466,8 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
 
 }  // namespace
 
-hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int64_t units_per_block,
-                                int nblocks, const double *omega, int nw, double *partial, hipStream_t s)
+hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
+                                const double *omega, int nw, double *partial, hipStream_t s)
 {
     if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
@@ -478,8 +475,8 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
     switch (slots) {
 #define C0_CASE(S)                                                                                       \
     case S:                                                                                              \
-        hipLaunchKernelGGL(tetra_dynamic_kernel<S>, grid, block, 0, s, mesh, batch, units_per_block,     \
-                           nblocks, omega, nw, partial);                                                 \
+        hipLaunchKernelGGL(tetra_dynamic_kernel<S>, grid, block, 0, s, mesh, batch, nblocks, omega, nw,  \
+                           partial);                                                                     \
         break;
         C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
 #undef C0_CASE
@@ -497,12 +494,12 @@ hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, con
     return hipGetLastError();
 }
 
-hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int64_t units_per_block,
-                               int nblocks, double *partial, hipStream_t s)
+hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
+                               hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
-    hipLaunchKernelGGL(tetra_static_kernel, grid, block, 0, s, mesh, batch, units_per_block, nblocks, partial);
+    hipLaunchKernelGGL(tetra_static_kernel, grid, block, 0, s, mesh, batch, nblocks, partial);
     return hipGetLastError();
 }
 
