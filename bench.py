@@ -23,11 +23,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations per evaluation, counted from the formulas the tetrahedron kernel evaluates
-# (a logarithm counted as 20 operations): see the roofline section of the design notes.
-FLOPS_FAR = 50       # d = w - c, 1/d, 24-term Horner, accumulate
-FLOPS_NEAR = 200     # 4 logs + leaf values/derivatives + 6 Newton entries with derivatives
-FLOPS_PREP = 350     # sort of 4 nodes + 24 far-series coefficients with derivatives
+# FP64 flops per evaluation, counted from the formulas the tetrahedron kernel evaluates
+# (an FMA counts 2, a reciprocal or division 1, a logarithm 20):
+#   far  (final tetrahedron, w): d = w - c (1), |d| rho test (1), reciprocal 1/d from the
+#        hardware estimate and two Newton steps (1 + 8), 40-term Horner (78), accumulate (2)
+#   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
+#        three 2-node entries (recursion 16 + 18-term series 181 + test 2: 600), two 3-node
+#        entries (recursion 16 + series 303 + test 2: 642), top entry 12, accumulate 2
+#   prep (per final tetrahedron): 40 far-series coefficients with W-derivatives (23 each) + 6
+FLOPS_FAR = 91
+FLOPS_NEAR = 1388
+FLOPS_PREP = 926
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 
 

@@ -236,86 +236,111 @@ C0_HD cplx hder_low(int n, double u, cplx L)
     }
 }
 
-// Value and W-derivative of the divided difference h[y_i..y_{i+P}] as a Taylor series of
-// kEntryTerms terms about the node c (one of its two end nodes), with u = w - c, L = Log(u):
-//   sum_m h^(P+m)(c)/(P+m)! H_m(y - c),  H_m of the offsets scaled by 1/u.
-// Exact to rounding when the span is at most kThetaEntry * |u|; computed for every lane
-// (no data-dependent trip count) and selected by the caller.
+// Value and W-derivative of a divided difference of h over P+1 nodes (P = 1, 2) as a
+// Taylor series of kEntryTerms terms about one of its nodes, e (u = w - y_e, L = Log(u)):
+//   h[..] = sum_m h^(P+m)(y_e)/(P+m)! H_m(y - y_e),
+// H_m the complete homogeneous symmetric polynomial of the offsets, scaled by 1/u.  The
+// offset of e itself is exactly 0, so H_m only runs over the other P offsets z (with
+// W-derivatives dz) and dH_m gains dz_e H_{m-1}.  Exact to rounding when the nodes lie within
+// kThetaEntry |u| of y_e; computed for every lane (no data-dependent trip count).
 constexpr int kEntryTerms = 18;
 
-template <int P>
-C0_HD void taylor_fixed(const double *y, const double *w, double c, double u, cplx L, cplx &val, cplx &tan)
+C0_HD double entry_coef(int n) { return 6.0 / ((double)n * (n - 1) * (n - 2) * (n - 3)); }
+
+// P = 1: nodes y_e and y_o.  H_m = z^m, dH_m = z^(m-1) (dz_e + m dz_o).
+C0_HD void taylor_pair(double ye, double we, double yo, double wo, double u, cplx L, cplx &val, cplx &tan)
 {
     const double inv = 1.0 / u;
-    double z[P + 1], dz[P + 1], Hp[P + 1], dHp[P + 1];
-#pragma unroll
-    for (int v = 0; v <= P; ++v) {
-        z[v] = (y[v] - c) * inv;
-        dz[v] = w[v] * inv;
-        Hp[v] = 1.0;
-        dHp[v] = 0.0;
-    }
-    const double up = (P == 1) ? u * u : u;      // u^(3-P)
-    val = cmk(0.0, 0.0);
+    const double z = (yo - ye) * inv, dze = we * inv, dzo = wo * inv;
+    // m = 0, 1, 2: the first, second and third derivative terms (logarithmic, complex)
+    const cplx h1 = hder_low(1, u, L), h2 = hder_low(2, u, L), h3 = hder_low(3, u, L);
+    val = h1;
     tan = cmk(0.0, 0.0);
-    double um = 1.0;
+    val = cfma(val, h2, u * z);
+    tan = cfma(tan, h2, u * (dze + dzo));
+    val = cfma(val, h3, u * u * z * z);
+    tan = cfma(tan, h3, u * u * z * (dze + 2.0 * dzo));
+    // m >= 3: real coefficients 6/(n(n-1)(n-2)(n-3)) u^2, n = m + 1
+    double zprev = z * z, sv = 0.0, st = 0.0;
 #pragma unroll
-    for (int m = 0; m < kEntryTerms; ++m) {
-        double H = 1.0, dH = 0.0;
-        if (m > 0) {
-            double prev = 0.0, dprev = 0.0;
-#pragma unroll
-            for (int v = 0; v <= P; ++v) {
-                const double nP = fma(z[v], Hp[v], prev);
-                const double ndP = fma(dz[v], Hp[v], fma(z[v], dHp[v], dprev));
-                Hp[v] = nP;
-                dHp[v] = ndP;
-                prev = nP;
-                dprev = ndP;
-            }
-            H = prev;
-            dH = dprev;
-        }
-        const int n = P + m;
-        if (n >= 4) {
-            const double nn = (double)n;
-            const double cf = 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0)) * up;
-            val.re = fma(cf, H, val.re);
-            tan.re = fma(cf, dH, tan.re);
-        } else {
-            const cplx hd = hder_low(n, u, L);
-            val = cfma(val, hd, um * H);
-            tan = cfma(tan, hd, um * dH);
-            um *= u;
-        }
+    for (int m = 3; m < kEntryTerms; ++m) {
+        const double zm = zprev * z;
+        const double cf = entry_coef(m + 1);
+        sv = fma(cf, zm, sv);
+        st = fma(cf * zprev, fma((double)m, dzo, dze), st);
+        zprev = zm;
     }
+    const double u2 = u * u;
+    val.re = fma(sv, u2, val.re);
+    tan.re = fma(st, u2, tan.re);
+}
+
+// P = 2: nodes y_e, y_1, y_2.  H_m = H_m(z1, z2) by the recurrence over the two offsets.
+C0_HD void taylor_triple(double ye, double we, double y1, double w1, double y2, double w2, double u, cplx L,
+                         cplx &val, cplx &tan)
+{
+    const double inv = 1.0 / u;
+    const double z1 = (y1 - ye) * inv, z2 = (y2 - ye) * inv;
+    const double dze = we * inv, dz1 = w1 * inv, dz2 = w2 * inv;
+    double A = 1.0, dA = 0.0, Bv = 1.0, dB = 0.0;      // H_m(z1), H_m(z1, z2) and derivatives
+    // m = 0, 1: the second and third derivative terms (logarithmic, complex)
+    const cplx h2 = hder_low(2, u, L), h3 = hder_low(3, u, L);
+    val = h2;
+    tan = cmk(0.0, 0.0);
+    {
+        const double nA = A * z1, ndA = dz1 * A + z1 * dA;
+        const double nB = fma(z2, Bv, nA), ndB = fma(dz2, Bv, fma(z2, dB, ndA));
+        const double dH = fma(dze, Bv, ndB);
+        val = cfma(val, h3, u * nB);
+        tan = cfma(tan, h3, u * dH);
+        A = nA; dA = ndA; Bv = nB; dB = ndB;
+    }
+    double sv = 0.0, st = 0.0;
+#pragma unroll
+    for (int m = 2; m < kEntryTerms; ++m) {
+        const double nA = A * z1, ndA = fma(dz1, A, z1 * dA);
+        const double nB = fma(z2, Bv, nA), ndB = fma(dz2, Bv, fma(z2, dB, ndA));
+        const double dH = fma(dze, Bv, ndB);
+        const double cf = entry_coef(m + 2);
+        sv = fma(cf, nB, sv);
+        st = fma(cf, dH, st);
+        A = nA; dA = ndA; Bv = nB; dB = ndB;
+    }
+    val.re = fma(sv, u, val.re);
+    tan.re = fma(st, u, tan.re);
 }
 
 C0_HD cplx csel(bool c, cplx a, cplx b) { return cmk(c ? a.re : b.re, c ? a.im : b.im); }
 
-// One Newton entry from its two children, or (when its nodes cluster within kThetaEntry of
-// their distance to w) from the Taylor series about its farther end node.
+// One Newton entry over nodes y[0..P] (P = 1, 2) from its two children A = [y_1..y_P] and
+// B = [y_0..y_{P-1}], or, when its nodes cluster within kThetaEntry of their distance to w,
+// from the Taylor series about its end node farther from w.
 template <int P>
 C0_HD void newton_entry(const double *y, const double *w, const double *u, const cplx *L, cplx A, cplx dA,
                         cplx B, cplx dB, cplx &V, cplx &T)
 {
-    // recursion: (A - B) / (y_P - y_0), A = [y_1..y_P], B = [y_0..y_{P-1}]
     const double span = y[P] - y[0];
     const double inv = 1.0 / span;
     const cplx E = cscale(csub(A, B), inv);
     const double dspan = (w[P] - w[0]) * inv;
     cplx dE = cscale(csub(dA, dB), inv);
     dE = cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
-    // series about the end node farther from w
     const double d0 = fabs(u[0]), dP = fabs(u[P]);
     const bool first = d0 >= dP;
     const double far = first ? d0 : dP;
-    const double uc = first ? u[0] : u[P];
-    const cplx Lc = csel(first, L[0], L[P]);
     const bool use_series = span <= kThetaEntry * far;
     const bool at_w = far == 0.0;                 // every node at w: h[..] and its derivative vanish
+    const double ue = at_w ? 1.0 : (first ? u[0] : u[P]);
+    const cplx Le = csel(first, L[0], L[P]);
     cplx Vt, Tt;
-    taylor_fixed<P>(y, w, first ? y[0] : y[P], at_w ? 1.0 : uc, Lc, Vt, Tt);
+    if (P == 1) {
+        taylor_pair(first ? y[0] : y[1], first ? w[0] : w[1], first ? y[1] : y[0], first ? w[1] : w[0], ue, Le, Vt,
+                    Tt);
+    } else {
+        // expansion node y[0] or y[2]; the other two in order
+        taylor_triple(first ? y[0] : y[P], first ? w[0] : w[P], first ? y[1] : y[0], first ? w[1] : w[0],
+                      first ? y[P] : y[1], first ? w[P] : w[1], ue, Le, Vt, Tt);
+    }
     if (at_w) { Vt = cmk(0.0, 0.0); Tt = cmk(0.0, 0.0); }
     V = csel(use_series, Vt, E);
     T = csel(use_series, Tt, dE);
