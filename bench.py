@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nq", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM byte counters)")
@@ -148,6 +149,32 @@ def main():
         "census": census,
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
     }
+
+    if not args.no_mixed:
+        # mixed form: split BF16 MFMA matrix elements, FP32 far-branch weights, FP64 fallback
+        # and FP64 accumulation; error against this run's FP64 result, per q (normwise over w)
+        ref64 = torch.view_as_complex(out).cpu().numpy()
+        res = {}
+        for prec, name in ((1, "bf16x3"), (2, "fp16x3")):
+            mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, precision=prec)
+            mout = torch.empty_like(out)
+            mplan.dynamic(qs, om, workspace=ws, out=mout)
+            torch.cuda.synchronize()
+            m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            m0.record(stream)
+            for i in range(args.steps):
+                mplan.dynamic(qs, om, workspace=ws, out=mout)
+            m1.record(stream)
+            torch.cuda.synchronize()
+            mms = m0.elapsed_time(m1) / args.steps
+            got = torch.view_as_complex(mout).cpu().numpy()
+            per_q = np.max(np.abs(got - ref64), axis=1) / np.max(np.abs(ref64), axis=1)
+            res[name] = {"value": units_per_step / (mms * 1e-3), "ms_per_step": mms,
+                         "speedup_vs_fp64": ms_step / mms, "max_rel_err_per_q_max": float(per_q.max()),
+                         "max_rel_err_per_q_mean": float(per_q.mean())}
+            log(f"mixed {name}: {mms:.1f} ms/step, max rel err {per_q.max():.2e}")
+            del mplan
+        result["mixed"] = res
 
     if not args.no_cpu_baseline:
         import oracle

@@ -71,7 +71,12 @@ typedef struct chi0_desc {
     int32_t form;           /* 0: occupation difference f(e)-f(e') (regions e<mu<e' minus e'<mu<e);
                                1: the paper's Eq. (1)/(2): region e<mu<e' only, with
                                   1/(w-D+i0) - 1/(w+D+i0)  (equal to form 0 under time reversal) */
-    int32_t precision;      /* 0: FP64 everywhere (the only value this build accepts) */
+    int32_t precision;      /* 0: FP64 everywhere.
+                               1: mixed: matrix elements from BF16 MFMA with hi+lo split operands
+                                  and FP32 accumulation; dynamic weights of far-cluster final
+                                  tetrahedra in FP32 (near and clustered ones, and the carving,
+                                  stay FP64); chi0 accumulated in FP64.
+                               2: as 1 with FP16 (low part scaled by 2^11) instead of BF16. */
     int32_t reserved[5];    /* must be zero */
     double mu;              /* Fermi level (energy units of the band arrays) */
     double spin_factor;     /* g_s, 2 for spin-degenerate bands */

@@ -174,7 +174,7 @@ chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *d, const double *eps_k,
     for (int i = 0; i < 5; ++i)
         if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;
     if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor)) return CHI0_E_NONFINITE;
-    if (d->precision != 0) return CHI0_E_UNSUPPORTED;
+    if (d->precision < 0 || d->precision > 2) return CHI0_E_INVALID_ARG;
     if (!eps_k) return CHI0_E_INVALID_ARG;
     if (!d->cma && !c_k) return CHI0_E_INVALID_ARG;
     // 6 Nk nbw^2 units must fit the 64-bit unit index and the per-q block count an int
@@ -293,7 +293,7 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
         if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract_f64(p->mesh, B, nqb, p->stream); })) != hipSuccess)
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, nqb, nblk, partial, p->stream); })) !=
             hipSuccess)
@@ -326,12 +326,13 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
         if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract_f64(p->mesh, B, nqb, p->stream); })) != hipSuccess)
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
             if ((e = timed(p, 1, [&] {
-                     return launch_tetra_dynamic(p->mesh, B, nqb, nblk, omega + w0, nwc, partial, p->stream);
+                     return launch_tetra_dynamic(p->mesh, B, nqb, nblk, omega + w0, nwc, partial, p->d.precision != 0,
+                                                 p->stream);
                  })) != hipSuccess)
                 return device_fail(p, e, "tetrahedron kernel");
             if ((e = timed(p, 2, [&] {
@@ -354,7 +355,7 @@ chi0_status chi0_matrix_elements(chi0_plan_t p, const chi0_q *q, double *W)
     Layout L = layout(p, 1, 1);
     BatchDev B;
     fill_batch(p, q, 0, 1, W, L, B);
-    hipError_t e = launch_contract_f64(p->mesh, B, 1, p->stream);
+    hipError_t e = launch_contract(p->mesh, B, 1, p->d.precision, p->stream);
     if (e != hipSuccess) return device_fail(p, e, "matrix-element kernel");
     return CHI0_OK;
 }

@@ -36,15 +36,17 @@ struct MeshDev {
 };
 
 // K_A: W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for nq q-points of a batch.
-hipError_t launch_contract_f64(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s);
+// precision 0: FP64 MFMA; 1: BF16 hi+lo split MFMA; 2: FP16 hi+lo split MFMA (FP32 accumulate).
+hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s);
 
 // K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
 hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
                                hipStream_t s);
 
 // K_B dynamic: per-block partial sums into partial[nq][nblocks][nw][2], nw <= kMaxOmegaPerLaunch.
+// mixed: far-branch series in FP32 (FP64 near branch and accumulation).
 hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
-                                const double *omega, int nw, double *partial, hipStream_t s);
+                                const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 
 // Census of the work of a dynamic call: counts[0..3] += active units, final tetrahedra,
 // near-branch and far-branch (final tetrahedron, frequency) evaluations.

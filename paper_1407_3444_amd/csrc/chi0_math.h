@@ -48,6 +48,9 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kFarTerms = CHI0_FAR_TERMS;          // series terms kept in the far branch
 constexpr double kRhoFar = CHI0_RHO_FAR;           // far branch when half-span <= kRhoFar * |w - c|
 constexpr double kThetaEntry = CHI0_THETA_ENTRY;   // series sub-entry when span <= kThetaEntry * |w - x_end|
+// Mixed-precision form: the far series in FP32 with kFarTerms32 terms (0.4^20 ~ 1e-8, the
+// FP32 resolution); near and clustered tetrahedra keep the FP64 evaluation.
+constexpr int kFarTerms32 = 20;
 
 struct cplx {
     double re, im;
@@ -195,13 +198,14 @@ C0_HD void sort4(double y[4], double w[4])
 
 // Far-branch coefficients: sum_j W_j J_j = sum_{m=1..K} a[m-1] t^m, t = 1/(w - c),
 // a_m = 6/(m(m+1)(m+2)(m+3)) * d/dW H_m(D - c)   (valid for half-span < |w - c|).
+template <int K = kFarTerms>
 C0_HD void far_coeffs(const double y[4], const double w[4], double c, double *a)
 {
     double z0 = y[0] - c, z1 = y[1] - c, z2 = y[2] - c, z3 = y[3] - c;
     double P0 = 1.0, P1 = 1.0, P2 = 1.0, P3 = 1.0;      // H_{m-1} over growing variable sets
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;      // their W-derivatives
 #pragma unroll
-    for (int m = 1; m <= kFarTerms; ++m) {
+    for (int m = 1; m <= K; ++m) {
         double n0 = z0 * P0;
         double e0 = fma(w[0], P0, z0 * d0);
         double n1 = fma(z1, P1, n0);

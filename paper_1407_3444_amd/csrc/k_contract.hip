@@ -91,14 +91,158 @@ __global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-precision form: 16-bit MFMA with FP32 accumulation and hi + lo operands.
+// Every FP64 operand x is split as x = hi + lo with hi = round16(x) and
+// lo = round16((x - hi) * S) / S (S = 2^11 for FP16, whose exponent range would flush
+// small remainders; S = 1 for BF16), and a product is taken as
+// hi*hi + (hi*lo + lo*hi) / S: three MFMAs, the dropped lo*lo term is below the FP32
+// accumulation error.  The complex product is folded into real GEMMs over a doubled
+// reduction axis:  Re M = [Cr Ci] . [Br; Bi],  Im M = [Cr Ci] . [Bi; -Br].
+// ---------------------------------------------------------------------------
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f)
+{
+    // round to nearest even (finite inputs)
+    const unsigned u = __float_as_uint(f);
+    return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+template <bool FP16>
+struct Split4 {
+    half4 hh, hl;
+    bf16x4 bh, bl;
+};
+
+template <bool FP16>
+__device__ __forceinline__ void split_value(double x, int j, Split4<FP16> &s)
+{
+    if (FP16) {
+        const _Float16 hi = (_Float16)x;
+        const _Float16 lo = (_Float16)((x - (double)hi) * 2048.0);
+        s.hh[j] = hi;
+        s.hl[j] = lo;
+    } else {
+        const short hi = to_bf16((float)x);
+        const short lo = to_bf16((float)(x - (double)from_bf16(hi)));
+        s.bh[j] = hi;
+        s.bl[j] = lo;
+    }
+}
+
+template <bool FP16>
+__device__ __forceinline__ flt4 mfma16(const Split4<FP16> &a, bool a_lo, const Split4<FP16> &b, bool b_lo, flt4 c)
+{
+    if (FP16)
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a_lo ? a.hl : a.hh, b_lo ? b.hl : b.hh, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_lo ? a.bl : a.bh, b_lo ? b.bl : b.bh, c, 0, 0, 0);
+}
+
+template <bool FP16>
+__global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev B)
+{
+    __shared__ double tile[16][16][kKPerBlock + 1];
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int lane = threadIdx.x;
+    const int row = lane & 15;      // A row (band n) / B column (band m)
+    const int kq4 = lane >> 4;      // which 4 of the 16 reduction indices of a step
+    const int64_t nk = M.nk;
+    const int64_t k0 = (int64_t)blockIdx.x * kKPerBlock;
+    const int ntile = (M.nbw + 15) / 16;
+    const int nb = M.nb, no = M.no;
+    const int kred = 2 * no;        // reduction axis: orbitals (real parts), then orbitals (imaginary)
+    const float inv_s = FP16 ? 1.0f / 2048.0f : 1.0f;
+
+    for (int tn = 0; tn < ntile; ++tn) {
+        for (int tm = 0; tm < ntile; ++tm) {
+            const int n = tn * 16 + row;
+            const int m = tm * 16 + row;
+            for (int kl = 0; kl < kKPerBlock; ++kl) {
+                const int64_t k = k0 + kl;
+                if (k >= nk) break;
+                int64_t kq = k;
+                if (!Q.explicit_kq) {
+                    int i2 = (int)(k % M.n3);
+                    const int64_t t = k / M.n3;
+                    int i1 = (int)(t % M.n2);
+                    int i0 = (int)(t / M.n2);
+                    i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
+                    i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
+                    i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
+                    kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
+                }
+                flt4 re_main = {0.f, 0.f, 0.f, 0.f}, re_corr = {0.f, 0.f, 0.f, 0.f};
+                flt4 im_main = {0.f, 0.f, 0.f, 0.f}, im_corr = {0.f, 0.f, 0.f, 0.f};
+                for (int r0 = 0; r0 < kred; r0 += 16) {
+                    Split4<FP16> a, bre, bim;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int r = r0 + 4 * kq4 + j;
+                        const bool imag = r >= no;
+                        const int o = imag ? r - no : r;
+                        double av = 0.0, brv = 0.0, biv = 0.0;
+                        if (r < kred && n < M.nbw) {
+                            const double *p = M.c_k + 2 * ((k * no + o) * nb + M.lo + n);
+                            av = imag ? p[1] : p[0];                // [Cr Ci]
+                        }
+                        if (r < kred && m < M.nbw) {
+                            const double *p = Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m);
+                            brv = imag ? p[1] : p[0];               // [Br; Bi]
+                            biv = imag ? -p[0] : p[1];              // [Bi; -Br]
+                        }
+                        split_value<FP16>(av, j, a);
+                        split_value<FP16>(brv, j, bre);
+                        split_value<FP16>(biv, j, bim);
+                    }
+                    re_main = mfma16<FP16>(a, false, bre, false, re_main);
+                    re_corr = mfma16<FP16>(a, false, bre, true, re_corr);
+                    re_corr = mfma16<FP16>(a, true, bre, false, re_corr);
+                    im_main = mfma16<FP16>(a, false, bim, false, im_main);
+                    im_corr = mfma16<FP16>(a, false, bim, true, im_corr);
+                    im_corr = mfma16<FP16>(a, true, bim, false, im_corr);
+                }
+                // accumulator element v of this lane is D[4 kq4 + v][row] for the 16x16x16 MFMA
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float mr = fmaf(re_corr[v], inv_s, re_main[v]);
+                    const float mi = fmaf(im_corr[v], inv_s, im_main[v]);
+                    tile[4 * kq4 + v][row][kl] = (double)(mr * mr + mi * mi);
+                }
+            }
+            __syncthreads();
+            for (int e = lane; e < 16 * 16 * kKPerBlock; e += 64) {
+                const int kl = e % kKPerBlock;
+                const int pj = e / kKPerBlock;
+                const int i = pj / 16, j = pj % 16;
+                const int nn = tn * 16 + i, mm = tm * 16 + j;
+                const int64_t k = k0 + kl;
+                if (nn < M.nbw && mm < M.nbw && k < nk) Q.W[((int64_t)nn * M.nbw + mm) * nk + k] = tile[i][j][kl];
+            }
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
 
-hipError_t launch_contract_f64(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s)
+hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;
     dim3 grid((unsigned)nblk, nq), block(64);
-    hipLaunchKernelGGL(contract_f64_kernel, grid, block, 0, s, mesh, batch);
+    if (precision == 1)
+        hipLaunchKernelGGL(contract_split_kernel<false>, grid, block, 0, s, mesh, batch);
+    else if (precision == 2)
+        hipLaunchKernelGGL(contract_split_kernel<true>, grid, block, 0, s, mesh, batch);
+    else
+        hipLaunchKernelGGL(contract_f64_kernel, grid, block, 0, s, mesh, batch);
     return hipGetLastError();
 }
 

@@ -35,7 +35,10 @@ constexpr int kQCap = 48;       // near-branch work items queued per lane
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W at the same corners
-    alignas(16) double a[kFarTerms];   // far-branch series coefficients
+    union {
+        alignas(16) double a[kFarTerms];     // far-branch series coefficients (FP64 form)
+        alignas(16) float a32[kFarTerms32];  // the same series, first kFarTerms32 terms (mixed form)
+    };
 };
 
 struct StatRec {
@@ -265,7 +268,7 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
     }
 }
 
-template <int NSLOT>
+template <int NSLOT, bool MIXED>
 __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
                                                            const double *__restrict__ omega, int nw,
                                                            double *__restrict__ partial)
@@ -314,7 +317,14 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
                 double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
                 double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
                 sort4(y, w);
-                far_coeffs(y, w, 0.5 * (y[0] + y[3]), list[r].a);
+                if (MIXED) {
+                    double a[kFarTerms32];
+                    far_coeffs<kFarTerms32>(y, w, 0.5 * (y[0] + y[3]), a);
+#pragma unroll
+                    for (int m = 0; m < kFarTerms32; ++m) list[r].a32[m] = (float)a[m];
+                } else {
+                    far_coeffs(y, w, 0.5 * (y[0] + y[3]), list[r].a);
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
             }
@@ -324,32 +334,61 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
                 // coefficients are read from LDS (broadcast) into registers in one burst
                 const double y0 = list[r].y[0], y3 = list[r].y[3];
                 const double c = 0.5 * (y0 + y3), hs = 0.5 * (y3 - y0);
-                double a[kFarTerms];
-#pragma unroll
-                for (int m = 0; m < kFarTerms; m += 2) {
-                    const double2 v = *reinterpret_cast<const double2 *>(&list[r].a[m]);
-                    a[m] = v.x;
-                    a[m + 1] = v.y;
-                }
-                double tt[NSLOT], f[NSLOT];
                 bool nearb[NSLOT];
+                if (MIXED) {
+                    float a[kFarTerms32];
 #pragma unroll
-                for (int s = 0; s < NSLOT; ++s) {
-                    const double d = om[s] - c;
-                    nearb[s] = !(hs <= kRhoFar * fabs(d));
-                    tt[s] = recip(nearb[s] ? 1.0 : d);
-                    f[s] = a[kFarTerms - 1];
+                    for (int m = 0; m < kFarTerms32; m += 4) {
+                        const float4 v = *reinterpret_cast<const float4 *>(&list[r].a32[m]);
+                        a[m] = v.x; a[m + 1] = v.y; a[m + 2] = v.z; a[m + 3] = v.w;
+                    }
+                    float tt[NSLOT], f[NSLOT];
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) {
+                        const double d = om[s] - c;          // the difference in FP64, then FP32
+                        nearb[s] = !(hs <= kRhoFar * fabs(d));
+                        const float df = (float)(nearb[s] ? 1.0 : d);
+                        float t = __builtin_amdgcn_rcpf(df);
+                        t = fmaf(t, fmaf(-df, t, 1.0f), t);
+                        tt[s] = t;
+                        f[s] = a[kFarTerms32 - 1];
+                    }
+#pragma unroll
+                    for (int m = kFarTerms32 - 2; m >= 0; --m) {
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) f[s] = fmaf(f[s], tt[s], a[m]);
+                    }
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s)
+                        if (!nearb[s]) acc[s].re += (double)(f[s] * tt[s]);
+                } else {
+                    double a[kFarTerms];
+#pragma unroll
+                    for (int m = 0; m < kFarTerms; m += 2) {
+                        const double2 v = *reinterpret_cast<const double2 *>(&list[r].a[m]);
+                        a[m] = v.x;
+                        a[m + 1] = v.y;
+                    }
+                    double tt[NSLOT], f[NSLOT];
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) {
+                        const double d = om[s] - c;
+                        nearb[s] = !(hs <= kRhoFar * fabs(d));
+                        tt[s] = recip(nearb[s] ? 1.0 : d);
+                        f[s] = a[kFarTerms - 1];
+                    }
+#pragma unroll
+                    for (int m = kFarTerms - 2; m >= 0; --m) {
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], a[m]);
+                    }
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s)
+                        if (!nearb[s]) acc[s].re = fma(f[s], tt[s], acc[s].re);
                 }
 #pragma unroll
-                for (int m = kFarTerms - 2; m >= 0; --m) {
-#pragma unroll
-                    for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], a[m]);
-                }
-#pragma unroll
                 for (int s = 0; s < NSLOT; ++s) {
-                    if (!nearb[s]) {
-                        acc[s].re = fma(f[s], tt[s], acc[s].re);
-                    } else if (live[s]) {
+                    if (nearb[s] && live[s]) {
                         queue[qn][lane] = (uint16_t)((r << 3) | s);
                         ++qn;
                     }
@@ -467,16 +506,20 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
 }  // namespace
 
 hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
-                                const double *omega, int nw, double *partial, hipStream_t s)
+                                const double *omega, int nw, double *partial, bool mixed, hipStream_t s)
 {
     if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
     const int slots = (nw + kWave - 1) / kWave;
-    switch (slots) {
-#define C0_CASE(S)                                                                                       \
-    case S:                                                                                              \
-        hipLaunchKernelGGL(tetra_dynamic_kernel<S>, grid, block, 0, s, mesh, batch, nblocks, omega, nw,  \
-                           partial);                                                                     \
+    switch (slots * 2 + (mixed ? 1 : 0)) {
+#define C0_CASE(S)                                                                                        \
+    case 2 * S:                                                                                           \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false>), grid, block, 0, s, mesh, batch, nblocks,     \
+                           omega, nw, partial);                                                           \
+        break;                                                                                            \
+    case 2 * S + 1:                                                                                       \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true>), grid, block, 0, s, mesh, batch, nblocks,      \
+                           omega, nw, partial);                                                           \
         break;
         C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
 #undef C0_CASE

@@ -66,7 +66,8 @@ def _plan(d, eps=FAKE, ck=FAKE):
     (dict(cma=3), -1),
     (dict(mu=float("nan")), -3),
     (dict(spin_factor=float("inf")), -3),
-    (dict(precision=1), -7),
+    (dict(precision=3), -1),
+    (dict(precision=-1), -1),
 ])
 def test_plan_rejects_bad_descriptors(kw, status):
     st, h = _plan(_desc(**kw))

@@ -192,3 +192,57 @@ def test_full_size_static_sampled_q():
     for i in range(2):
         ref = oracle.chi0(wl, i)[0].real
         assert abs(got[i] - ref) <= TOL * abs(ref), (i, got[i], ref)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 2e-5), (2, 1e-6)])
+def test_matrix_elements_split_precision(precision, tol):
+    """BF16x3 (1) and FP16x3 (2) split-product MFMA against the plain contraction."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    m = synth.tetragonal_two_site_model(2)
+    wl = synth.model_workload(m, (8, 8, 4), [np.array([0.13, 0.31, 0.07])], np.zeros(1), static=True)
+    dev = torch.device("cuda:0")
+    plan = lib.Chi0Plan(wl.nk, torch.from_numpy(wl.eps_k).to(dev), torch.from_numpy(wl.c_k).to(dev),
+                        precision=precision)
+    q = wl.qs[0]
+    _say("split-precision matrix elements, precision", precision)
+    W = plan.matrix_elements(lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev),
+                                   c_kq=torch.from_numpy(q.c_kq).to(dev))).cpu().numpy()
+    ref = np.abs(np.einsum("kon,kom->nmk", wl.c_k.conj(), q.c_kq)) ** 2
+    err = np.max(np.abs(W - ref))
+    _say("max abs W error", err)
+    assert err < tol
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_dynamic_mixed_precision_error(precision):
+    """Mixed form (split MFMA matrix elements, FP32 far-branch weights, FP64 fallback and
+    accumulation) against the FP64 oracle: max relative error per q <= 1e-5."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    wl = synth.make_workload("tetra_dynamic", nk=(10, 10, 4), nq=8, q_subset=[2, 5], nw=128)
+    dev = torch.device("cuda:0")
+    plan = lib.Chi0Plan(wl.nk, torch.from_numpy(wl.eps_k).to(dev), torch.from_numpy(wl.c_k).to(dev),
+                        precision=precision)
+    qs = [lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev), c_kq=torch.from_numpy(q.c_kq).to(dev)) for q in wl.qs]
+    _say("dynamic mixed precision", precision)
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).to(dev)).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i)
+        err = _relerr(got[i], ref)
+        _say(f"q {i}: max rel err {err:.2e}")
+        assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n_keep", [9, 5])
+def test_full_size_bcc_band_windows_sampled(n_keep):
+    """The 9-orbital bcc model on the full 48^3 mesh (663,552 tetrahedra), one q of the (010)
+    path, 512 w, with the 9-band sum and a 5-band truncation; the oracle checks 2 frequencies."""
+    torch = _torch()
+    wl = synth.make_workload("bcc_dynamic", q_subset=[20], n_keep=n_keep, workers=8)
+    plan, qs = _plan(wl)
+    _say("full-size bcc 48^3, window", wl.window())
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    sample = [37, 290]
+    ref = oracle.chi0(wl, 0, omega=wl.omega[sample])
+    assert _relerr(got[0][sample], ref) <= TOL, (got[0][sample], ref)
