@@ -4,11 +4,16 @@ Default workload (the precision-study configuration of the 10-orbital model): th
 seeded two-site tetragonal tight-binding model (10 d-like orbitals, seed 2) on a
 64 x 64 x 8 mesh (196,608 tetrahedra), all 100 band pairs, 64 q at the arc-length
 midpoints of Gamma-X-M-Gamma (explicit k+q eigenpairs), 512 frequencies on [0, 2] eV,
-dynamic chi0 (analytic Re, delta-weight Im), FP64.
+dynamic chi0 (analytic Re, delta-weight Im), FP64, with the mixed-precision forms
+timed beside it.
 
-One step = one chi0_dynamic call over all 64 q x 512 w: matrix elements (MFMA),
-carving + tetrahedron weights, ordered reduction.  Inputs are resident in HBM before
-the timed region.  Prints one JSON line.
+One step = one chi0_dynamic call over all q x w: matrix elements (MFMA), carving +
+tetrahedron weights, ordered reduction.  Inputs are resident in HBM before the timed
+region.  Prints one JSON line.
+
+--workload selects the other seeded configurations: bcc_dynamic (9-orbital bcc, 48^3,
+64 q x 512 w, --n-keep band window), tetra_static (the 10-orbital model, 256 q, static)
+and sc_cma (single-band cubic, 16^3, 8 q, static).
 """
 from __future__ import annotations
 
@@ -36,9 +41,86 @@ FLOPS_NEAR = 1388
 FLOPS_PREP = 926
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 
+# HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
+# rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
+# the kernel sources with this hash only (see the counter summary under profiles/).
+TRAFFIC_KERNEL_SHA = "e363f65673dff653"
+TRAFFIC_BYTES_PER_LAUNCH = (426465 * 2.0 + 196601 * 1.0) * 1024
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_tetra.hip", "chi0_math.h"):
+        with open(os.path.join(ROOT, "paper_1407_3444_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def upload(wl, dev):
+    import torch
+    import paper_1407_3444_amd as lib
+    eps = torch.from_numpy(wl.eps_k).to(dev)
+    ck = None if wl.c_k is None else torch.from_numpy(wl.c_k).to(dev)
+    qs = []
+    for q in wl.qs:
+        if q.shift is not None:
+            qs.append(lib.Q(shift=q.shift))
+        else:
+            c = None if (q.c_kq is None or wl.cma) else torch.from_numpy(q.c_kq).to(dev)
+            qs.append(lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev), c_kq=c))
+    return eps, ck, qs
+
+
+def bench_static(args, wl, desc):
+    """Static chi0 over all q of a static workload: one chi0_static call per step."""
+    import torch
+    import paper_1407_3444_amd as lib
+    dev = torch.device("cuda:0")
+    eps, ck, qs = upload(wl, dev)
+    lo, hi = wl.window()
+    nbw = hi - lo
+    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
+                        cma=wl.cma)
+    ws = plan.workspace(len(qs), 1)
+    out = torch.empty(len(qs), dtype=torch.float64, device=dev)
+    for _ in range(max(1, args.warmup)):
+        plan.static(qs, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.read_profile()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.static(qs, workspace=ws, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    prof = plan.read_profile()
+    units = len(qs) * 6 * wl.n_k * nbw * nbw
+    result = {"metric": "chi0 band-pair*tetra*omega updates/s (FP64 GPU)", "value": units / (ms * 1e-3),
+              "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+              "data": "synthetic (seeded tight-binding model, eigenpairs by numpy eigh)",
+              "config": {"workload": desc, "mesh": list(wl.nk), "n_q": len(qs), "n_omega": 1,
+                         "band_pairs": nbw * nbw, "units_per_step": units, "parallelism": "single GPU"},
+              "roofline": None,
+              "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.time()
+        ref = oracle.chi0(wl, 0, nthreads=threads)[0].real
+        dt = time.time() - t1
+        result["cpu_baseline"] = {"value": 6 * wl.n_k * nbw * nbw / dt, "unit": "updates/s", "cores": threads,
+                                  "kind": "oracle", "sample": f"q index 0 of {len(qs)}, full mesh, {dt:.1f} s"}
+        result["parity_sample"] = {"rel_err_vs_oracle": abs(float(out[0].item()) - ref) / abs(ref), "q": 0}
+    print(json.dumps(result), flush=True)
 
 
 def main():
@@ -49,6 +131,9 @@ def main():
     ap.add_argument("--nq", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--workload", default="tetra_dynamic",
+                    choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma"])
+    ap.add_argument("--n-keep", type=int, default=9, help="band window of bcc_dynamic")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM byte counters)")
@@ -70,17 +155,35 @@ def main():
 
     import synth
     t0 = time.time()
-    wl = synth.make_workload("tetra_dynamic", nq=64, q_subset=list(range(args.nq)), workers=args.workers)
+    if args.workload == "tetra_dynamic":
+        wl = synth.make_workload("tetra_dynamic", nq=64, q_subset=list(range(min(args.nq, 64))),
+                                 workers=args.workers)
+        desc = ("tetragonal two-site 10-orbital TB, 64x64x8 mesh, 64 q x 512 w, dynamic, all 100 band "
+                "pairs, FP64")
+    elif args.workload == "bcc_dynamic":
+        wl = synth.make_workload("bcc_dynamic", nq=64, q_subset=list(range(min(args.nq, 64))),
+                                 n_keep=args.n_keep, workers=args.workers)
+        desc = f"bcc 9-orbital TB, 48^3 mesh, 64 q x 512 w, dynamic, {args.n_keep}-band window, FP64"
+    elif args.workload == "tetra_static":
+        nq = 256 if args.nq == 64 else args.nq
+        wl = synth.make_workload("tetra_static", nq=256, q_subset=list(range(min(nq, 256))),
+                                 workers=args.workers)
+        desc = "tetragonal two-site 10-orbital TB, 64x64x8 mesh, 256 q, static, all 100 band pairs, FP64"
+    else:
+        wl = synth.make_workload("sc_cma")
+        desc = "single-band simple-cubic NN TB, CMA, 16^3 mesh, 8 q on Gamma-R, static, FP64"
     log(f"inputs built in {time.time() - t0:.1f}s: mesh {wl.nk}, {len(wl.qs)} q, {len(wl.omega)} w")
+    if wl.static:
+        return bench_static(args, wl, desc)
 
     import torch
     import paper_1407_3444_amd as lib
     dev = torch.device("cuda:0")
-    eps = torch.from_numpy(wl.eps_k).to(dev)
-    ck = torch.from_numpy(wl.c_k).to(dev)
-    qs = [lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev), c_kq=torch.from_numpy(q.c_kq).to(dev)) for q in wl.qs]
+    eps, ck, qs = upload(wl, dev)
     om = torch.from_numpy(wl.omega).to(dev)
-    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor)
+    lo, hi = wl.window()
+    nbw = hi - lo
+    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi)
     ws = plan.workspace(len(qs), len(wl.omega))
     out = torch.empty((len(qs), len(wl.omega), 2), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -110,7 +213,7 @@ def main():
     log("timed", args.steps, "steps:", f"{ms_total:.1f} ms", prof)
 
     nw = len(wl.omega)
-    units_per_step = len(qs) * 6 * wl.n_k * 100 * nw
+    units_per_step = len(qs) * 6 * wl.n_k * nbw * nbw * nw
     ms_step = ms_total / args.steps
     value = units_per_step * args.steps / (ms_total * 1e-3)
 
@@ -121,8 +224,11 @@ def main():
                       + census["final_tetrahedra"] * FLOPS_PREP)
     flops_per_launch = flops_per_step / launches_per_step
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    traffic = None
+    if args.workload == "tetra_dynamic" and len(qs) == 64 and kernel_sha() == TRAFFIC_KERNEL_SHA:
+        traffic = TRAFFIC_BYTES_PER_LAUNCH
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "tetra_dynamic_kernel", "avg_launch_ms": round(avg_ms, 3),
                 "launches_per_step": launches_per_step}
 
@@ -139,9 +245,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded tight-binding model, eigenpairs by numpy eigh)",
-        "config": {"workload": "tetragonal two-site 10-orbital TB, 64x64x8 mesh, 64 q x 512 w, dynamic, "
-                               "all 100 band pairs, FP64",
-                   "mesh": list(wl.nk), "n_q": len(qs), "n_omega": nw, "band_pairs": 100,
+        "config": {"workload": desc,
+                   "mesh": list(wl.nk), "n_q": len(qs), "n_omega": nw, "band_pairs": nbw * nbw,
                    "tetrahedra": 6 * wl.n_k, "units_per_step": units_per_step,
                    "active_units_per_step": census["active_units"] * nw,
                    "parallelism": "single GPU"},
@@ -156,7 +261,8 @@ def main():
         ref64 = torch.view_as_complex(out).cpu().numpy()
         res = {}
         for prec, name in ((1, "bf16x3"), (2, "fp16x3")):
-            mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, precision=prec)
+            mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo,
+                                 band_hi=hi, precision=prec)
             mout = torch.empty_like(out)
             mplan.dynamic(qs, om, workspace=ws, out=mout)
             torch.cuda.synchronize()
@@ -183,12 +289,12 @@ def main():
         t1 = time.time()
         ref = oracle.chi0(wl, 0, omega=wl.omega[sample_w], nthreads=threads)
         dt = time.time() - t1
-        units = 6 * wl.n_k * 100 * len(sample_w)
+        units = 6 * wl.n_k * nbw * nbw * len(sample_w)
         got = torch.view_as_complex(out[0]).cpu().numpy()[sample_w]
         err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
         result["cpu_baseline"] = {"value": units / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-                                  "sample": f"q index 0, {len(sample_w)} of 512 w, full 64x64x8 mesh, "
-                                            f"{dt:.1f} s"}
+                                  "sample": f"q index 0, {len(sample_w)} of {nw} w, full "
+                                            f"{'x'.join(map(str, wl.nk))} mesh, {dt:.1f} s"}
         result["parity_sample"] = {"max_rel_err_vs_oracle": err, "q": 0, "omega_index": sample_w}
         log(f"oracle sample {dt:.1f}s, rel err {err:.2e}")
     print(json.dumps(result), flush=True)
