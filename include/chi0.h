@@ -146,6 +146,81 @@ chi0_status chi0_census(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t 
                         const double *omega, void *workspace, size_t workspace_bytes,
                         uint64_t *counts);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched form: many independent instances (each a plan-like problem with its own mesh, bands,
+ * q-list and frequency grid) run as one fused sequence of three launches -- matrix elements,
+ * tetrahedron weights, reduction -- over a flat table of (instance, q, frequency-chunk) items,
+ * optionally captured once into a HIP graph and replayed.  Each item computes exactly what
+ * chi0_dynamic computes for that instance and q (same kernels, same summation order for a given
+ * number of workgroups per item), so the batched result equals the per-instance calls to
+ * rounding of the block partition.
+ * ------------------------------------------------------------------------------------------ */
+
+typedef struct chi0_instance {
+    chi0_desc desc;         /* as for chi0_plan (validated the same way) */
+    const double *eps_k;    /* device [n_bands][Nk] float64 */
+    const double *c_k;      /* device [Nk][n_orb][n_bands] complex128; NULL under cma */
+    int32_t nq;             /* q-points of this instance, >= 1 */
+    int32_t nw;             /* frequencies, >= 1 (static problems: nw = 1, omega = {0}) */
+    const chi0_q *qs;       /* host [nq]; copied by chi0_batch_create */
+    const double *omega;    /* device [nw] float64 */
+    double *chi;            /* device [nq][nw][2] float64 output (Re, Im) */
+} chi0_instance;
+
+typedef struct chi0_batch_opts {
+    int64_t workgroups;     /* tetrahedron-kernel workgroups of the whole batch, spread over the
+                               items in proportion to their estimated cost (each item gets
+                               1..1024 and at most one per 64 units); 0 = 32768.  The workspace
+                               is sized for this value; chi0_batch_tune only tries smaller ones. */
+    uint64_t stage_w_bytes; /* most bytes of matrix elements W resident at once: (instance, q)
+                               groups are run in stages whose W fits (a group larger than the
+                               limit runs alone); 0 = one stage */
+    int32_t use_graph;      /* 1: capture the launch sequence into a HIP graph on the first run
+                               and replay it afterwards; 0: launch directly every run */
+    int32_t reserved[5];    /* must be zero */
+} chi0_batch_opts;
+
+typedef struct chi0_batch_s *chi0_batch_t;
+
+/* Device workspace (bytes) a batch of n_inst instances needs (opts may be NULL = defaults). */
+chi0_status chi0_batch_workspace_size(int32_t n_inst, const chi0_instance *inst,
+                                      const chi0_batch_opts *opts, size_t *bytes);
+
+/* Validate the instances, schedule the items and write the item tables into the workspace
+ * (a synchronous upload on hip_stream).  The batch borrows every device pointer of every
+ * instance and the workspace; they must stay valid while the batch exists.  Nothing is
+ * computed until chi0_batch_run. */
+chi0_status chi0_batch_create(chi0_batch_t *out, int32_t n_inst, const chi0_instance *inst,
+                              const chi0_batch_opts *opts, void *workspace, size_t workspace_bytes,
+                              void *hip_stream);
+
+/* Compute chi0 of every instance into its chi array, asynchronously on hip_stream (NULL = the
+ * default stream).  Runs that overlap on different streams race on the workspace. */
+chi0_status chi0_batch_run(chi0_batch_t batch, void *hip_stream);
+
+/* Autotune the number of workgroups: after one warm-up run, time reps runs at the workgroup
+ * count the batch was created with and at 1/2, 1/4 and 1/8 of it (not below one per item),
+ * keep the fastest (synchronises hip_stream; leaves valid results in the outputs).  *chosen
+ * (may be NULL) receives it. */
+chi0_status chi0_batch_tune(chi0_batch_t batch, void *hip_stream, int32_t reps, int64_t *chosen);
+
+/* Schedule summary of a batch (host struct). */
+typedef struct chi0_batch_info {
+    int64_t items;          /* (instance, q, frequency chunk) items */
+    int64_t stages;         /* W-budget stages (launch triples) */
+    int64_t workgroups[3];  /* workgroups of the matrix-element, tetrahedron and reduction
+                               launches, summed over stages */
+    int64_t nominal_units;  /* sum over instances of nq * 6 Nk * nbw^2 * nw */
+} chi0_batch_info;
+
+chi0_status chi0_batch_info_get(chi0_batch_t batch, chi0_batch_info *info);
+
+/* Release a batch (host memory and its graph, if any).  NULL is accepted. */
+chi0_status chi0_batch_destroy(chi0_batch_t batch);
+
+/* Text of the last error recorded on this batch ("" if none). */
+const char *chi0_batch_last_error(chi0_batch_t batch);
+
 /* Release a plan (host memory only).  NULL is accepted. */
 chi0_status chi0_destroy(chi0_plan_t plan);
 

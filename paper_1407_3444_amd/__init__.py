@@ -16,13 +16,16 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
-__all__ = ["Chi0Plan", "Q", "Chi0Error", "load_library", "LIB_PATH", "EXPORTED_SYMBOLS"]
+__all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library", "LIB_PATH",
+           "EXPORTED_SYMBOLS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
 EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
-                    "chi0_destroy", "chi0_status_string", "chi0_last_error"]
+                    "chi0_destroy", "chi0_status_string", "chi0_last_error", "chi0_batch_workspace_size",
+                    "chi0_batch_create", "chi0_batch_run", "chi0_batch_tune", "chi0_batch_info_get",
+                    "chi0_batch_destroy", "chi0_batch_last_error"]
 
 STATUS = {0: "CHI0_OK", -1: "CHI0_E_INVALID_ARG", -2: "CHI0_E_SHAPE", -3: "CHI0_E_NONFINITE",
           -5: "CHI0_E_WORKSPACE", -6: "CHI0_E_DEVICE", -7: "CHI0_E_UNSUPPORTED"}
@@ -44,6 +47,22 @@ class _Desc(ctypes.Structure):
 class _Q(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int32 * 3), ("explicit_kq", ctypes.c_int32),
                 ("eps_kq", ctypes.c_void_p), ("c_kq", ctypes.c_void_p)]
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("desc", _Desc), ("eps_k", ctypes.c_void_p), ("c_k", ctypes.c_void_p), ("nq", ctypes.c_int32),
+                ("nw", ctypes.c_int32), ("qs", ctypes.POINTER(_Q)), ("omega", ctypes.c_void_p),
+                ("chi", ctypes.c_void_p)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int64), ("stage_w_bytes", ctypes.c_uint64), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int64), ("stages", ctypes.c_int64), ("workgroups", ctypes.c_int64 * 3),
+                ("nominal_units", ctypes.c_int64)]
 
 
 class _Profile(ctypes.Structure):
@@ -75,9 +94,20 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_status_string.restype = ctypes.c_char_p
     lib.chi0_last_error.argtypes = [vp]
     lib.chi0_last_error.restype = ctypes.c_char_p
+    lib.chi0_batch_workspace_size.argtypes = [i32, ctypes.POINTER(_Instance), ctypes.POINTER(_BatchOpts),
+                                              ctypes.POINTER(sz)]
+    lib.chi0_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_Instance), ctypes.POINTER(_BatchOpts),
+                                      vp, sz, vp]
+    lib.chi0_batch_run.argtypes = [vp, vp]
+    lib.chi0_batch_tune.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.chi0_batch_info_get.argtypes = [vp, ctypes.POINTER(_BatchInfo)]
+    lib.chi0_batch_destroy.argtypes = [vp]
+    lib.chi0_batch_last_error.argtypes = [vp]
+    lib.chi0_batch_last_error.restype = ctypes.c_char_p
     for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
-                 "chi0_destroy"):
+                 "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
+                 "chi0_batch_tune", "chi0_batch_info_get", "chi0_batch_destroy"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -104,6 +134,28 @@ def _dev_ptr(t, dtype_name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _make_desc(nk, eps_k, c_k, mu, spin_factor, band_lo, band_hi, cma, form, precision) -> _Desc:
+    d = _Desc()
+    for i in range(3):
+        d.nk[i] = int(nk[i])
+    d.n_bands = int(eps_k.shape[0])
+    d.n_orb = 1 if c_k is None else int(c_k.shape[1])
+    d.band_lo, d.band_hi = int(band_lo), int(band_hi)
+    d.cma, d.form, d.precision = int(bool(cma)), int(form), int(precision)
+    d.mu, d.spin_factor = float(mu), float(spin_factor)
+    return d
+
+
+def _q_struct(q: "Q", dst: _Q):
+    if q.eps_kq is not None:
+        dst.explicit_kq = 1
+        dst.eps_kq = _dev_ptr(q.eps_kq, "torch.float64")
+        dst.c_kq = _dev_ptr(q.c_kq, "torch.complex128")
+    else:
+        for a in range(3):
+            dst.shift[a] = int(q.shift[a])
+
+
 class Chi0Plan:
     """A chi0 plan over fixed mesh band data (eps_k [nb][Nk], c_k [Nk][no][nb] on the device)."""
 
@@ -115,14 +167,7 @@ class Chi0Plan:
         self.nk = tuple(int(v) for v in nk)
         self.eps_k = eps_k
         self.c_k = c_k
-        d = _Desc()
-        for i in range(3):
-            d.nk[i] = self.nk[i]
-        d.n_bands = int(eps_k.shape[0])
-        d.n_orb = 1 if c_k is None else int(c_k.shape[1])
-        d.band_lo, d.band_hi = int(band_lo), int(band_hi)
-        d.cma, d.form, d.precision = int(bool(cma)), int(form), int(precision)
-        d.mu, d.spin_factor = float(mu), float(spin_factor)
+        d = _make_desc(self.nk, eps_k, c_k, mu, spin_factor, band_lo, band_hi, cma, form, precision)
         self.nbw = (d.n_bands if band_hi <= 0 else band_hi) - band_lo
         self.cma = bool(cma)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -151,13 +196,7 @@ class Chi0Plan:
     def _qarray(self, qs: Sequence[Q]):
         arr = (_Q * len(qs))()
         for i, q in enumerate(qs):
-            if q.eps_kq is not None:
-                arr[i].explicit_kq = 1
-                arr[i].eps_kq = _dev_ptr(q.eps_kq, "torch.float64")
-                arr[i].c_kq = _dev_ptr(q.c_kq, "torch.complex128")
-            else:
-                for a in range(3):
-                    arr[i].shift[a] = int(q.shift[a])
+            _q_struct(q, arr[i])
         return arr
 
     def workspace_bytes(self, nq: int, nw: int) -> int:
@@ -226,3 +265,110 @@ class Chi0Plan:
         self._check(st, "chi0_census")
         return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
                 "near_evals": int(counts[2]), "far_evals": int(counts[3])}
+
+
+@dataclass
+class Instance:
+    """One problem of a batch: mesh band data, its q-list and frequency grid (device tensors).
+
+    chi (complex128 [nq, nw], allocated by Chi0Batch when None) receives chi0(q, w)."""
+    nk: Sequence[int]
+    eps_k: object
+    c_k: Optional[object]
+    qs: Sequence[Q]
+    omega: object
+    mu: float = 0.0
+    spin_factor: float = 2.0
+    band_lo: int = 0
+    band_hi: int = 0
+    cma: bool = False
+    form: int = 0
+    precision: int = 0
+    chi: Optional[object] = None
+
+
+class Chi0Batch:
+    """Many instances run as one fused launch sequence (optionally a replayed HIP graph)."""
+
+    def __init__(self, instances: Sequence[Instance], *, workgroups: int = 0, stage_w_bytes: int = 0,
+                 use_graph: bool = True, stream=None):
+        import torch
+        self._lib = load_library()
+        self.instances = list(instances)
+        n = len(self.instances)
+        self._inst = (_Instance * n)()
+        self._qarrs = []
+        dev = self.instances[0].eps_k.device
+        for i, ins in enumerate(self.instances):
+            nw = int(ins.omega.shape[0])
+            if ins.chi is None:
+                ins.chi = torch.empty((len(ins.qs), nw, 2), dtype=torch.float64, device=dev)
+            elif ins.chi.dtype == torch.complex128:
+                ins.chi = torch.view_as_real(ins.chi)
+            qa = (_Q * len(ins.qs))()
+            for j, q in enumerate(ins.qs):
+                _q_struct(q, qa[j])
+            self._qarrs.append(qa)
+            s = self._inst[i]
+            s.desc = _make_desc(ins.nk, ins.eps_k, ins.c_k, ins.mu, ins.spin_factor, ins.band_lo, ins.band_hi,
+                                ins.cma, ins.form, ins.precision)
+            s.eps_k = _dev_ptr(ins.eps_k, "torch.float64")
+            s.c_k = _dev_ptr(ins.c_k, "torch.complex128")
+            s.nq, s.nw = len(ins.qs), nw
+            s.qs = ctypes.cast(qa, ctypes.POINTER(_Q))
+            s.omega = _dev_ptr(ins.omega, "torch.float64")
+            s.chi = _dev_ptr(ins.chi, "torch.float64")
+        self._opts = _BatchOpts()
+        self._opts.workgroups = int(workgroups)
+        self._opts.stage_w_bytes = int(stage_w_bytes)
+        self._opts.use_graph = int(bool(use_graph))
+        nbytes = ctypes.c_size_t()
+        st = self._lib.chi0_batch_workspace_size(n, self._inst, ctypes.byref(self._opts), ctypes.byref(nbytes))
+        if st != 0:
+            raise Chi0Error(st, "chi0_batch_workspace_size rejected the instances")
+        self.workspace = torch.empty(max(1, int(nbytes.value)), dtype=torch.uint8, device=dev)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = ctypes.c_void_p()
+        st = self._lib.chi0_batch_create(ctypes.byref(handle), n, self._inst, ctypes.byref(self._opts),
+                                         ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                         ctypes.c_void_p(self._stream.cuda_stream))
+        if st != 0:
+            raise Chi0Error(st, "chi0_batch_create failed")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.chi0_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != 0:
+            raise Chi0Error(st, f"{what}: {self._lib.chi0_batch_last_error(self._h).decode()}")
+
+    def run(self, stream=None):
+        """Enqueue the whole batch; returns the instances' chi as complex128 views."""
+        import torch
+        s = stream if stream is not None else self._stream
+        self._check(self._lib.chi0_batch_run(self._h, ctypes.c_void_p(s.cuda_stream)), "chi0_batch_run")
+        return [torch.view_as_complex(ins.chi) for ins in self.instances]
+
+    def tune(self, reps: int = 2, stream=None) -> int:
+        s = stream if stream is not None else self._stream
+        chosen = ctypes.c_int64()
+        self._check(self._lib.chi0_batch_tune(self._h, ctypes.c_void_p(s.cuda_stream), int(reps),
+                                              ctypes.byref(chosen)), "chi0_batch_tune")
+        return int(chosen.value)
+
+    def info(self) -> dict:
+        inf = _BatchInfo()
+        self._check(self._lib.chi0_batch_info_get(self._h, ctypes.byref(inf)), "chi0_batch_info_get")
+        return {"items": int(inf.items), "stages": int(inf.stages),
+                "workgroups": {"contract": int(inf.workgroups[0]), "tetra": int(inf.workgroups[1]),
+                               "reduce": int(inf.workgroups[2])},
+                "nominal_units": int(inf.nominal_units)}

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "chi0_host.h"
 #include "chi0_internal.h"
 
 using namespace chi0;
@@ -88,12 +89,9 @@ chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
 {
     if (nq < 1 || !qs) return fail(p, CHI0_E_INVALID_ARG, "nq must be >= 1 and qs non-null");
     for (int i = 0; i < nq; ++i) {
-        const chi0_q &q = qs[i];
-        if (q.explicit_kq != 0 && q.explicit_kq != 1) return fail(p, CHI0_E_INVALID_ARG, "explicit_kq must be 0 or 1");
-        if (q.explicit_kq) {
-            if (!q.eps_kq) return fail(p, CHI0_E_INVALID_ARG, "explicit q without eps_kq");
-            if (!p->d.cma && !q.c_kq) return fail(p, CHI0_E_INVALID_ARG, "explicit q without c_kq");
-        }
+        const char *msg = "";
+        const chi0_status st = check_q(p->d, qs[i], &msg);
+        if (st) return fail(p, st, msg);
     }
     return CHI0_OK;
 }
@@ -101,20 +99,10 @@ chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
 void fill_batch(const chi0_plan_s *p, const chi0_q *qs, int q0, int nqb, void *ws, const Layout &L, BatchDev &B)
 {
     std::memset(&B, 0, sizeof B);
-    const int n[3] = {p->mesh.n1, p->mesh.n2, p->mesh.n3};
     for (int i = 0; i < nqb; ++i) {
-        const chi0_q &q = qs[q0 + i];
-        QDev &d = B.q[i];
-        d.explicit_kq = q.explicit_kq;
-        if (q.explicit_kq) {
-            d.eps_kq = q.eps_kq;
-            d.c_kq = q.c_kq;
-        } else {
-            d.eps_kq = p->mesh.eps_k;
-            d.c_kq = p->mesh.c_k;
-            for (int a = 0; a < 3; ++a) d.shift[a] = ((q.shift[a] % n[a]) + n[a]) % n[a];
-        }
-        d.W = p->d.cma ? nullptr : reinterpret_cast<double *>(static_cast<char *>(ws) + L.w_off + L.w_bytes_per_q * i);
+        double *W = p->d.cma ? nullptr
+                             : reinterpret_cast<double *>(static_cast<char *>(ws) + L.w_off + L.w_bytes_per_q * i);
+        B.q[i] = make_qdev(p->mesh, qs[q0 + i], W);
     }
 }
 
@@ -138,6 +126,91 @@ hipError_t timed(chi0_plan_s *p, int kind, F &&launch)
 
 }  // namespace
 
+namespace chi0 {
+
+chi0_status check_desc(const chi0_desc *d, const double *eps_k, const double *c_k)
+{
+    if (!d) return CHI0_E_INVALID_ARG;
+    for (int i = 0; i < 3; ++i)
+        if (d->nk[i] < 1) return CHI0_E_SHAPE;
+    const int64_t nk = (int64_t)d->nk[0] * d->nk[1] * d->nk[2];
+    if (nk >= (int64_t(1) << 31)) return CHI0_E_SHAPE;
+    if (d->n_bands < 1 || d->n_bands > 64) return CHI0_E_SHAPE;
+    const int hi = d->band_hi <= 0 ? d->n_bands : d->band_hi;
+    if (d->band_lo < 0 || d->band_lo >= hi || hi > d->n_bands) return CHI0_E_SHAPE;
+    if (hi - d->band_lo > 32) return CHI0_E_SHAPE;
+    if (d->cma != 0 && d->cma != 1) return CHI0_E_INVALID_ARG;
+    if (!d->cma && (d->n_orb < 1 || d->n_orb > 64)) return CHI0_E_SHAPE;
+    if (d->form != 0 && d->form != 1) return CHI0_E_INVALID_ARG;
+    for (int i = 0; i < 5; ++i)
+        if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;
+    if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor)) return CHI0_E_NONFINITE;
+    if (d->precision < 0 || d->precision > 2) return CHI0_E_INVALID_ARG;
+    if (!eps_k) return CHI0_E_INVALID_ARG;
+    if (!d->cma && !c_k) return CHI0_E_INVALID_ARG;
+    return CHI0_OK;
+}
+
+MeshDev make_mesh(const chi0_desc &d, const double *eps_k, const double *c_k)
+{
+    MeshDev M;
+    std::memset(&M, 0, sizeof M);
+    const int hi = d.band_hi <= 0 ? d.n_bands : d.band_hi;
+    M.n1 = d.nk[0];
+    M.n2 = d.nk[1];
+    M.n3 = d.nk[2];
+    M.nk = (int64_t)d.nk[0] * d.nk[1] * d.nk[2];
+    M.nb = d.n_bands;
+    M.no = d.cma ? 1 : d.n_orb;
+    M.lo = d.band_lo;
+    M.nbw = hi - d.band_lo;
+    M.cma = d.cma;
+    M.form = d.form;
+    M.mu = d.mu;
+    M.eps_k = eps_k;
+    M.c_k = c_k;
+    return M;
+}
+
+chi0_status check_q(const chi0_desc &d, const chi0_q &q, const char **msg)
+{
+    if (q.explicit_kq != 0 && q.explicit_kq != 1) {
+        *msg = "explicit_kq must be 0 or 1";
+        return CHI0_E_INVALID_ARG;
+    }
+    if (q.explicit_kq) {
+        if (!q.eps_kq) {
+            *msg = "explicit q without eps_kq";
+            return CHI0_E_INVALID_ARG;
+        }
+        if (!d.cma && !q.c_kq) {
+            *msg = "explicit q without c_kq";
+            return CHI0_E_INVALID_ARG;
+        }
+    }
+    return CHI0_OK;
+}
+
+QDev make_qdev(const MeshDev &M, const chi0_q &q, double *W)
+{
+    QDev d;
+    std::memset(&d, 0, sizeof d);
+    const int n[3] = {M.n1, M.n2, M.n3};
+    d.explicit_kq = q.explicit_kq;
+    if (q.explicit_kq) {
+        d.eps_kq = q.eps_kq;
+        d.c_kq = q.c_kq;
+    } else {
+        d.eps_kq = M.eps_k;
+        d.c_kq = M.c_k;
+        for (int a = 0; a < 3; ++a) d.shift[a] = ((q.shift[a] % n[a]) + n[a]) % n[a];
+    }
+    d.W = M.cma ? nullptr : W;
+    return d;
+}
+
+}  // namespace chi0
+
 extern "C" {
 
 const char *chi0_status_string(chi0_status s)
@@ -158,44 +231,15 @@ const char *chi0_last_error(chi0_plan_t p) { return p ? p->err.c_str() : ""; }
 
 chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *d, const double *eps_k, const double *c_k, void *stream)
 {
-    if (!out || !d) return CHI0_E_INVALID_ARG;
+    if (!out) return CHI0_E_INVALID_ARG;
     *out = nullptr;
-    for (int i = 0; i < 3; ++i)
-        if (d->nk[i] < 1) return CHI0_E_SHAPE;
-    const int64_t nk = (int64_t)d->nk[0] * d->nk[1] * d->nk[2];
-    if (nk >= (int64_t(1) << 31)) return CHI0_E_SHAPE;
-    if (d->n_bands < 1 || d->n_bands > 64) return CHI0_E_SHAPE;
-    const int hi = d->band_hi <= 0 ? d->n_bands : d->band_hi;
-    if (d->band_lo < 0 || d->band_lo >= hi || hi > d->n_bands) return CHI0_E_SHAPE;
-    if (hi - d->band_lo > 32) return CHI0_E_SHAPE;
-    if (d->cma != 0 && d->cma != 1) return CHI0_E_INVALID_ARG;
-    if (!d->cma && (d->n_orb < 1 || d->n_orb > 64)) return CHI0_E_SHAPE;
-    if (d->form != 0 && d->form != 1) return CHI0_E_INVALID_ARG;
-    for (int i = 0; i < 5; ++i)
-        if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;
-    if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor)) return CHI0_E_NONFINITE;
-    if (d->precision < 0 || d->precision > 2) return CHI0_E_INVALID_ARG;
-    if (!eps_k) return CHI0_E_INVALID_ARG;
-    if (!d->cma && !c_k) return CHI0_E_INVALID_ARG;
-    // 6 Nk nbw^2 units must fit the 64-bit unit index and the per-q block count an int
+    const chi0_status st = check_desc(d, eps_k, c_k);
+    if (st) return st;
     chi0_plan_s *p = new (std::nothrow) chi0_plan_s();
     if (!p) return CHI0_E_INVALID_ARG;
     p->d = *d;
-    p->d.band_hi = hi;
-    MeshDev &M = p->mesh;
-    M.n1 = d->nk[0];
-    M.n2 = d->nk[1];
-    M.n3 = d->nk[2];
-    M.nk = nk;
-    M.nb = d->n_bands;
-    M.no = d->cma ? 1 : d->n_orb;
-    M.lo = d->band_lo;
-    M.nbw = hi - d->band_lo;
-    M.cma = d->cma;
-    M.form = d->form;
-    M.mu = d->mu;
-    M.eps_k = eps_k;
-    M.c_k = c_k;
+    p->mesh = make_mesh(*d, eps_k, c_k);
+    p->d.band_hi = p->mesh.lo + p->mesh.nbw;
     p->stream = static_cast<hipStream_t>(stream);
     *out = p;
     return CHI0_OK;

@@ -35,6 +35,29 @@ struct MeshDev {
     const double *c_k;      // [Nk][no][nb] complex
 };
 
+// One (instance, q) item of a fused batch launch (device table entry).
+struct BatchItemDev {
+    MeshDev M;
+    QDev Q;
+    const double *omega;   // [nw]
+    double *partial;       // this item's K_B partial sums [nblocks][nw][2]
+    double *out;           // chi of this q: [nw][2]
+    double scale;          // g_s / (6 Nk)
+    int32_t nw, precision;
+    int32_t nblocks;       // K_B workgroups of this item
+    int32_t kb_begin;      // first K_B workgroup of the item in the fused grid
+    int32_t ka_begin;      // first K_A workgroup (16 k each), -1 under CMA
+    int32_t kr_begin;      // first K_R workgroup (256 values each)
+};
+
+// Fused launches over a batch table: matrix elements, tetrahedron weights, reduction.
+hipError_t launch_contract_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
+                                 hipStream_t s);
+hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
+                              hipStream_t s);
+hipError_t launch_reduce_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
+                               hipStream_t s);
+
 // K_A: W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for nq q-points of a batch.
 // precision 0: FP64 MFMA; 1: BF16 hi+lo split MFMA; 2: FP16 hi+lo split MFMA (FP32 accumulate).
 hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s);

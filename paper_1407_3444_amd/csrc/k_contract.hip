@@ -19,16 +19,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKPerBlock = 16;
 
-__global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B)
+typedef double Tile[16][kKPerBlock + 1];
+
+// One workgroup of FP64 matrix elements: k = k0 .. k0+15 of one q.
+__device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &Q, int64_t k0, Tile *tile)
 {
-    __shared__ double tile[16][16][kKPerBlock + 1];
-    const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
     const int row = lane & 15;      // A row (band n) / B column (band m) of this lane
     const int kk = lane >> 4;       // orbital within the step of 4
     const int64_t nk = M.nk;
-    const int64_t k0 = (int64_t)blockIdx.x * kKPerBlock;
     const int ntile = (M.nbw + 15) / 16;
     const int nb = M.nb, no = M.no;
 
@@ -144,17 +143,14 @@ __device__ __forceinline__ flt4 mfma16(const Split4<FP16> &a, bool a_lo, const S
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_lo ? a.bl : a.bh, b_lo ? b.bl : b.bh, c, 0, 0, 0);
 }
 
+// One workgroup of split-precision matrix elements: k = k0 .. k0+15 of one q.
 template <bool FP16>
-__global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev B)
+__device__ __forceinline__ void contract_split_body(const MeshDev &M, const QDev &Q, int64_t k0, Tile *tile)
 {
-    __shared__ double tile[16][16][kKPerBlock + 1];
-    const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
     const int row = lane & 15;      // A row (band n) / B column (band m)
     const int kq4 = lane >> 4;      // which 4 of the 16 reduction indices of a step
     const int64_t nk = M.nk;
-    const int64_t k0 = (int64_t)blockIdx.x * kKPerBlock;
     const int ntile = (M.nbw + 15) / 16;
     const int nb = M.nb, no = M.no;
     const int kred = 2 * no;        // reduction axis: orbitals (real parts), then orbitals (imaginary)
@@ -230,7 +226,43 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
     }
 }
 
+__global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B)
+{
+    __shared__ double tile[16][16][kKPerBlock + 1];
+    contract_f64_body(M, B.q[blockIdx.y], (int64_t)blockIdx.x * kKPerBlock, tile);
+}
+
+template <bool FP16>
+__global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev B)
+{
+    __shared__ double tile[16][16][kKPerBlock + 1];
+    contract_split_body<FP16>(M, B.q[blockIdx.y], (int64_t)blockIdx.x * kKPerBlock, tile);
+}
+
+// Fused launch over the (instance, q) items of a batch: workgroup -> item from a table.
+__global__ __launch_bounds__(64) void contract_batch_kernel(const BatchItemDev *__restrict__ items,
+                                                            const int32_t *__restrict__ block_item)
+{
+    __shared__ double tile[16][16][kKPerBlock + 1];
+    const BatchItemDev it = items[block_item[blockIdx.x]];
+    const int64_t k0 = (int64_t)(blockIdx.x - it.ka_begin) * kKPerBlock;
+    if (it.precision == 1)
+        contract_split_body<false>(it.M, it.Q, k0, tile);
+    else if (it.precision == 2)
+        contract_split_body<true>(it.M, it.Q, k0, tile);
+    else
+        contract_f64_body(it.M, it.Q, k0, tile);
+}
+
 }  // namespace
+
+hipError_t launch_contract_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
+                                 hipStream_t s)
+{
+    if (nblocks_total < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(contract_batch_kernel, dim3(nblocks_total), dim3(64), 0, s, items, block_item);
+    return hipGetLastError();
+}
 
 hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s)
 {

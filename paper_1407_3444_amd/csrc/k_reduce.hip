@@ -7,13 +7,8 @@ namespace chi0 {
 
 namespace {
 
-__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int nblocks, int nvals,
-                                                     double scale, double *__restrict__ out, int64_t out_stride)
+__device__ __forceinline__ double ordered_sum(const double *__restrict__ p, int nblocks, int nvals)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    const int q = blockIdx.y;
-    if (v >= nvals) return;
-    const double *p = partial + (int64_t)q * nblocks * nvals + v;
     // four independent running sums (fixed assignment b % 4) combined in a fixed order
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int b = 0;
@@ -24,10 +19,37 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ 
         s3 += p[(int64_t)(b + 3) * nvals];
     }
     for (; b < nblocks; ++b) s0 += p[(int64_t)b * nvals];
-    out[(int64_t)q * out_stride + v] = scale * ((s0 + s1) + (s2 + s3));
+    return (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const BatchItemDev *__restrict__ items,
+                                                           const int32_t *__restrict__ block_item)
+{
+    const BatchItemDev it = items[block_item[blockIdx.x]];
+    const int nvals = 2 * it.nw;
+    const int v = (blockIdx.x - it.kr_begin) * blockDim.x + threadIdx.x;
+    if (v >= nvals) return;
+    it.out[v] = it.scale * ordered_sum(it.partial + v, it.nblocks, nvals);
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int nblocks, int nvals,
+                                                     double scale, double *__restrict__ out, int64_t out_stride)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (v >= nvals) return;
+    out[(int64_t)q * out_stride + v] = scale * ordered_sum(partial + (int64_t)q * nblocks * nvals + v, nblocks, nvals);
 }
 
 }  // namespace
+
+hipError_t launch_reduce_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
+                               hipStream_t s)
+{
+    if (nblocks_total < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3(nblocks_total), dim3(256), 0, s, items, block_item);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale, double *out,
                          int64_t out_stride, hipStream_t s)

@@ -199,15 +199,6 @@ __device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, int64_
     return nrec;
 }
 
-__device__ __forceinline__ double uniform(double x)
-{
-    // a wave-uniform value moved to scalar registers
-    const unsigned long long b = __double_as_longlong(x);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
 // 1/d to full FP64 precision: hardware reciprocal estimate + two Newton steps
 __device__ __forceinline__ double recip(double d)
 {
@@ -215,29 +206,6 @@ __device__ __forceinline__ double recip(double d)
     t = fma(t, fma(-d, t, 1.0), t);
     t = fma(t, fma(-d, t, 1.0), t);
     return t;
-}
-
-template <int K>
-__device__ __forceinline__ double horner(const double *a, double t)
-{
-    double s = a[K - 1];
-#pragma unroll
-    for (int m = K - 2; m >= 0; --m) s = fma(s, t, a[m]);
-    return s * t;
-}
-
-__device__ __forceinline__ double wave_min(double x)
-{
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmin(x, __shfl_xor(x, d, kWave));
-    return x;
-}
-
-__device__ __forceinline__ double wave_max(double x)
-{
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, kWave));
-    return x;
 }
 
 // Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.
@@ -268,17 +236,14 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
     }
 }
 
+// One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
+// partial sums for every frequency to part[nw][2].
 template <int NSLOT, bool MIXED>
-__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
-                                                           const double *__restrict__ omega, int nw,
-                                                           double *__restrict__ partial)
+__device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, int nblocks, int blk,
+                                             const double *__restrict__ omega, int nw, double *__restrict__ part,
+                                             DynRec *list, uint16_t (*queue)[kWave])
 {
-    __shared__ DynRec list[kCapDyn];
-    __shared__ uint16_t queue[kQCap][kWave];
-    const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
-    const int blk = blockIdx.x;
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
 
     // frequencies of this lane (slot s holds w[lane + 64 s]) and each slot's range over the wave
@@ -403,10 +368,46 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
     for (int s = 0; s < NSLOT; ++s) {
         const int idx = lane + kWave * s;
         if (idx < nw) {
-            double *p = partial + (((int64_t)qi * nblocks + blk) * nw + idx) * 2;
-            p[0] = acc[s].re;
-            p[1] = acc[s].im;
+            part[2 * idx] = acc[s].re;
+            part[2 * idx + 1] = acc[s].im;
         }
+    }
+}
+
+template <int NSLOT, bool MIXED>
+__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
+                                                           const double *__restrict__ omega, int nw,
+                                                           double *__restrict__ partial)
+{
+    __shared__ DynRec list[kCapDyn];
+    __shared__ uint16_t queue[kQCap][kWave];
+    const int qi = blockIdx.y;
+    dynamic_body<NSLOT, MIXED>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
+                               partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue);
+}
+
+// Fused launch over the (instance, q) items of a batch: workgroup -> item from a table, then the
+// item's own frequency count and precision select the instantiation.
+__global__ __launch_bounds__(64) void tetra_batch_kernel(const BatchItemDev *__restrict__ items,
+                                                         const int32_t *__restrict__ block_item)
+{
+    __shared__ DynRec list[kCapDyn];
+    __shared__ uint16_t queue[kQCap][kWave];
+    const BatchItemDev it = items[block_item[blockIdx.x]];
+    const int blk = blockIdx.x - it.kb_begin;
+    double *part = it.partial + (int64_t)blk * it.nw * 2;
+    const int slots = (it.nw + kWave - 1) / kWave;
+    switch (slots * 2 + (it.precision != 0 ? 1 : 0)) {
+#define C0_CASE(S)                                                                                        \
+    case 2 * S:                                                                                           \
+        dynamic_body<S, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);          \
+        break;                                                                                            \
+    case 2 * S + 1:                                                                                       \
+        dynamic_body<S, true>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);           \
+        break;
+        C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
+#undef C0_CASE
+    default: break;
     }
 }
 
@@ -525,6 +526,13 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
 #undef C0_CASE
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total, hipStream_t s)
+{
+    if (nblocks_total < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tetra_batch_kernel, dim3(nblocks_total), dim3(kWave), 0, s, items, block_item);
     return hipGetLastError();
 }
 

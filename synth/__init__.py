@@ -32,7 +32,7 @@ __all__ = [
     "TBModel", "mesh_kfrac", "eigensystem", "sc_nn_model", "tetragonal_two_site_model",
     "bcc_spd_model", "random_model", "free_electron_eps", "Workload", "QPoint",
     "make_workload", "gamma_x_m_gamma_midpoints", "bcc_gamma_h_gamma_path", "omega_grid",
-    "band_window", "random_commensurate_shifts",
+    "band_window", "random_commensurate_shifts", "batch_workloads",
 ]
 
 
@@ -377,3 +377,31 @@ def model_workload(model: TBModel, nk, q_fracs: Sequence, omega: np.ndarray, sta
         for q in q_fracs:
             qs.append(_explicit_q(model, kf, np.asarray(q, dtype=np.float64)))
     return Workload(model.name, nk, eps, c, qs, np.asarray(omega, dtype=np.float64), static=static, **kw)
+
+
+def batch_workloads(nq_div: int = 1, precision: int = 0) -> List[Tuple[Workload, int]]:
+    """The 16-instance heterogeneous batch (seeds 500..515).
+
+    Instance i: lattice family tetragonal / bcc / sc in turn, n_orb = 4 + round(28 i / 15) orbitals
+    (all bands kept), an L^3 mesh with L = 48, 40, 32, 24 for i in blocks of four, nq = 128 -
+    round(96 i / 15) random non-zero commensurate mesh shifts (divided by nq_div, at least 1) and
+    nw = 512 - round(384 i / 15) frequencies on [0, 2] eV.  Large meshes pair with few orbitals
+    and many q and frequencies, so the per-instance work stays within a factor of a few.
+    Returns (workload, precision) pairs.
+    """
+    kinds = ("tetragonal", "bcc", "sc")
+    out = []
+    for i in range(16):
+        seed = 500 + i
+        n_orb = 4 + int(round(28 * i / 15))
+        L = (48, 40, 32, 24)[i // 4]
+        nq = max(1, (128 - int(round(96 * i / 15))) // nq_div)
+        nw = 512 - int(round(384 * i / 15))
+        model = random_model(kinds[i % 3], seed, n_orb)
+        rng = np.random.default_rng(seed)
+        shifts = random_commensurate_shifts(rng, (L, L, L), nq)
+        wl = model_workload(model, (L, L, L), None, omega_grid(nw), shifts=shifts)
+        wl.name = "batch%02d_%s" % (i, model.name)
+        wl.meta = {"model": model.name, "seed": seed, "n_orb": n_orb, "mesh": L, "nq": nq, "nw": nw}
+        out.append((wl, precision))
+    return out

@@ -120,3 +120,77 @@ def test_workspace_grows_with_frequencies_up_to_one_launch():
         assert sizes[0] < sizes[1] < sizes[2] == sizes[3]
     finally:
         so.chi0_destroy(h)
+
+
+def _instance(nq=3, nw=100, **kw):
+    ins = lib._Instance()
+    ins.desc = _desc(**kw)
+    ins.eps_k = FAKE
+    ins.c_k = None if kw.get("cma") else FAKE
+    qa = (lib._Q * max(nq, 1))()
+    for j in range(max(nq, 1)):
+        qa[j].shift[0] = j + 1
+    ins.nq, ins.nw = nq, nw
+    ins.qs = ctypes.cast(qa, ctypes.POINTER(lib._Q))
+    ins.omega = ctypes.c_void_p(0x4000)
+    ins.chi = ctypes.c_void_p(0x5000)
+    return ins, qa
+
+
+def _batch_size(insts, **opt):
+    so = lib.load_library()
+    arr = (lib._Instance * len(insts))(*insts)
+    o = lib._BatchOpts()
+    o.workgroups = opt.get("workgroups", 0)
+    o.stage_w_bytes = opt.get("stage_w_bytes", 0)
+    o.use_graph = opt.get("use_graph", 0)
+    if "reserved" in opt:
+        o.reserved[0] = opt["reserved"]
+    n = ctypes.c_size_t()
+    st = so.chi0_batch_workspace_size(len(insts), arr, ctypes.byref(o), ctypes.byref(n))
+    return st, n.value
+
+
+def test_batch_validates_instances_on_the_host():
+    a, qa = _instance(nk=(8, 8, 8))
+    b, qb = _instance(nq=2, nw=700, nk=(6, 6, 6), n_bands=6, n_orb=5, band_lo=1, band_hi=5)
+    st, n = _batch_size([a, b])
+    assert st == 0 and n > 0
+    bad, qbad = _instance(nk=(8, 0, 8))
+    assert _batch_size([a, bad])[0] == -2
+    assert _batch_size([_instance(nq=0)[0]])[0] == -1
+    assert _batch_size([_instance(nw=0)[0]])[0] == -1
+    assert _batch_size([a], reserved=1)[0] == -1
+    assert _batch_size([a], use_graph=2)[0] == -1
+    c, qc = _instance()
+    c.qs = None
+    assert _batch_size([c])[0] == -1
+    d, qd = _instance()
+    qd[1].explicit_kq = 1                     # explicit q without its arrays
+    assert _batch_size([d])[0] == -1
+    so = lib.load_library()
+    assert so.chi0_batch_workspace_size(0, None, None, ctypes.byref(ctypes.c_size_t())) == -1
+    assert so.chi0_batch_destroy(None) == 0
+
+
+def test_batch_workspace_follows_workgroups_and_stage_budget():
+    insts = [_instance(nq=4, nw=300, nk=(12, 12, 12), n_bands=8, n_orb=8)[0] for _ in range(3)]
+    w_bytes = 8 * 8 * 8 * 12 ** 3                       # W of one q
+    sizes = [_batch_size(insts, workgroups=g)[1] for g in (256, 1024, 4096)]
+    assert sizes[0] <= sizes[1] <= sizes[2]
+    one_stage = _batch_size(insts)[1]
+    staged = _batch_size(insts, stage_w_bytes=2 * w_bytes)[1]
+    # one stage holds W of all 12 (instance, q) groups; budgeted stages hold two at a time
+    assert one_stage - staged >= 9 * w_bytes
+
+
+def test_batch_create_checks_the_workspace_before_device_work():
+    so = lib.load_library()
+    a, qa = _instance(nk=(8, 8, 8))
+    arr = (lib._Instance * 1)(a)
+    h = ctypes.c_void_p()
+    st, need = _batch_size([a])
+    assert st == 0
+    assert so.chi0_batch_create(ctypes.byref(h), 1, arr, None, None, need, None) == -5
+    assert so.chi0_batch_create(ctypes.byref(h), 1, arr, None, ctypes.c_void_p(0x6000), need - 256, None) == -5
+    assert not h.value
