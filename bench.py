@@ -31,12 +31,15 @@ sys.path.insert(0, ROOT)
 # FP64 flops per evaluation, counted from the formulas the tetrahedron kernel evaluates
 # (an FMA counts 2, a reciprocal or division 1, a logarithm 20):
 #   far  (final tetrahedron, w): d = w - c (1), |d| rho test (1), reciprocal 1/d from the
-#        hardware estimate and two Newton steps (1 + 8), 40-term Horner (78), accumulate (2)
+#        hardware estimate and two Newton steps (1 + 8), accumulate (2): 11 + 2 per series term
+#        (the census counts the terms each far evaluation uses; a Horner FMA per term beyond
+#        the first, so an n-term series costs 11 + 2 n)
 #   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
 #        three 2-node entries (recursion 16 + 18-term series 181 + test 2: 600), two 3-node
 #        entries (recursion 16 + series 303 + test 2: 642), top entry 12, accumulate 2
 #   prep (per final tetrahedron): 40 far-series coefficients with W-derivatives (23 each) + 6
-FLOPS_FAR = 91
+FLOPS_FAR_BASE = 11
+FLOPS_PER_TERM = 2
 FLOPS_NEAR = 1388
 FLOPS_PREP = 926
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
@@ -46,6 +49,12 @@ FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 # the kernel sources with this hash only (see the counter summary under profiles/).
 TRAFFIC_KERNEL_SHA = "e363f65673dff653"
 TRAFFIC_BYTES_PER_LAUNCH = (426465 * 2.0 + 196601 * 1.0) * 1024
+
+
+def census_flops(census: dict) -> int:
+    """Algorithmic FP64 flops of a dynamic call from its work census."""
+    return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
+            + census["near_evals"] * FLOPS_NEAR + census["final_tetrahedra"] * FLOPS_PREP)
 
 
 def kernel_sha() -> str:
@@ -159,7 +168,7 @@ def bench_batch(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     seq_out = [torch.empty((len(i.qs), int(i.omega.shape[0]), 2), dtype=torch.float64, device=dev)
                for i in insts]
-    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0}
+    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0}
     for p, i in zip(plans, insts):
         c = p.census(i.qs, i.omega, workspace=ws)
         for k in census:
@@ -194,8 +203,7 @@ def bench_batch(args):
     log(f"batched mixed (graph): {m_ms:.1f} ms/step, max rel err {per_q.max():.2e}")
     mbatch.close()
 
-    flops = (census["far_evals"] * FLOPS_FAR + census["near_evals"] * FLOPS_NEAR
-             + census["final_tetrahedra"] * FLOPS_PREP)
+    flops = census_flops(census)
     achieved = flops / (b_ms * 1e-3) / 1e12
     result = {
         "metric": "chi0 band-pair*tetra*omega updates/s (FP64 GPU)",
@@ -340,8 +348,7 @@ def main():
     tet = prof["tetra"]
     launches_per_step = tet["launches"] / args.steps
     avg_ms = tet["ms"] / tet["launches"]
-    flops_per_step = (census["far_evals"] * FLOPS_FAR + census["near_evals"] * FLOPS_NEAR
-                      + census["final_tetrahedra"] * FLOPS_PREP)
+    flops_per_step = census_flops(census)
     flops_per_launch = flops_per_step / launches_per_step
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     traffic = None

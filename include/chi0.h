@@ -138,10 +138,12 @@ chi0_status chi0_profile_enable(chi0_plan_t plan, int32_t enable);
 chi0_status chi0_profile_read(chi0_plan_t plan, chi0_profile *out);
 
 /* Work census of chi0_dynamic(plan, nq, qs, nw, omega) without evaluating it (diagnostic):
- * counts (host uint64 [4]) receives the number of (tetrahedron, band pair, q) units whose
- * carved region is non-empty, the number of final tetrahedra, and the number of (final
+ * counts (host uint64 [5]) receives the number of (tetrahedron, band pair, q) units whose
+ * carved region is non-empty, the number of final tetrahedra, the number of (final
  * tetrahedron, frequency) evaluations taking the near branch and the far branch of the
- * weight evaluation.  Uses the same workspace as chi0_dynamic and synchronises the stream. */
+ * weight evaluation, and the far-series terms summed over the far evaluations (each group
+ * of 64 frequencies is cut to the terms its distance from the tetrahedron needs).  Uses the
+ * same workspace as chi0_dynamic and synchronises the stream. */
 chi0_status chi0_census(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
                         const double *omega, void *workspace, size_t workspace_bytes,
                         uint64_t *counts);

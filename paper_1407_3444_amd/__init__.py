@@ -259,12 +259,12 @@ class Chi0Plan:
         nq, nw = len(qs), int(omega.shape[0])
         ws = workspace if workspace is not None else self.workspace(nq, nw)
         arr = self._qarray(qs)
-        counts = (ctypes.c_uint64 * 4)()
+        counts = (ctypes.c_uint64 * 5)()
         st = self._lib.chi0_census(self._h, nq, arr, nw, _dev_ptr(omega, "torch.float64"),
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), counts)
         self._check(st, "chi0_census")
         return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
-                "near_evals": int(counts[2]), "far_evals": int(counts[3])}
+                "near_evals": int(counts[2]), "far_evals": int(counts[3]), "far_terms": int(counts[4])}
 
 
 @dataclass

@@ -293,20 +293,25 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
     const Layout L = layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch));
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
-    hipError_t e = hipMemsetAsync(dc, 0, 4 * sizeof(unsigned long long), p->stream);
+    hipError_t e = hipMemsetAsync(dc, 0, 5 * sizeof(unsigned long long), p->stream);
     if (e != hipSuccess) return device_fail(p, e, "census clear");
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
         fill_batch(p, qs, q0, nqb, ws, L, B);
-        if ((e = launch_census(p->mesh, B, nqb, omega, nw, dc, p->stream)) != hipSuccess)
-            return device_fail(p, e, "census kernel");
+        for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
+            const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
+            if ((e = launch_census(p->mesh, B, nqb, omega + w0, nwc, p->d.precision != 0, w0 == 0, dc,
+                                   p->stream)) !=
+                hipSuccess)
+                return device_fail(p, e, "census kernel");
+        }
     }
-    unsigned long long h[4];
+    unsigned long long h[5];
     if ((e = hipMemcpyAsync(h, dc, sizeof h, hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(p->stream)) != hipSuccess)
         return device_fail(p, e, "census copy");
-    for (int i = 0; i < 4; ++i) counts[i] = h[i];
+    for (int i = 0; i < 5; ++i) counts[i] = h[i];
     return CHI0_OK;
 }
 

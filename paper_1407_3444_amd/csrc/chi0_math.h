@@ -41,12 +41,14 @@ constexpr double kPi = 3.14159265358979323846;
 #ifndef CHI0_FAR_TERMS
 #define CHI0_FAR_TERMS 40
 #define CHI0_RHO_FAR 0.4
+#define CHI0_LOG2_INV_RHO_FAR 1.3219280948873623   // log2(1 / CHI0_RHO_FAR)
 #endif
 #ifndef CHI0_THETA_ENTRY
 #define CHI0_THETA_ENTRY 0.1
 #endif
 constexpr int kFarTerms = CHI0_FAR_TERMS;          // series terms kept in the far branch
 constexpr double kRhoFar = CHI0_RHO_FAR;           // far branch when half-span <= kRhoFar * |w - c|
+constexpr double kLog2InvRhoFar = CHI0_LOG2_INV_RHO_FAR;
 constexpr double kThetaEntry = CHI0_THETA_ENTRY;   // series sub-entry when span <= kThetaEntry * |w - x_end|
 // Mixed-precision form: the far series in FP32 with kFarTerms32 terms (0.4^20 ~ 1e-8, the
 // FP32 resolution); near and clustered tetrahedra keep the FP64 evaluation.
@@ -227,6 +229,51 @@ C0_HD double far_horner(const double *a, double t)
 #pragma unroll
     for (int m = kFarTerms - 2; m >= 0; --m) s = fma(s, t, a[m]);
     return s * t;
+}
+
+// Truncation of the far series for a group of frequencies (all frequencies one wave evaluates
+// together, i.e. those of one launch).  A frequency of the group that takes the far branch has
+// |w - c| >= max(dist, hs / kRhoFar), dist = distance from c to the group's frequency interval,
+// so its ratio hs / |w - c| is at most rho_g = min(kRhoFar, hs / dist).  The remainder after n
+// terms is bounded by a factor polynomial in n times rho_g^n |t|, so n <= K terms with
+// rho_g^n <= kRhoFar^K keep the error bound of the full K-term series at the largest ratio
+// kRhoFar.  The group gets class
+// j = 1..kFarClasses (n = j K / kFarClasses terms), the smallest j with
+// j >= kFarClasses ln(kRhoFar) / ln(rho_g); class 0 when every frequency of the group is near.
+constexpr int kFarClasses = 10;
+
+C0_HD int far_class(double hs, double dist, double dfar)
+{
+    if (!(hs <= kRhoFar * dfar)) return 0;              // the farthest frequency is near too
+    if (!(hs < kRhoFar * dist)) return kFarClasses;     // rho_g = kRhoFar (also dist = 0)
+    // j = ceil(kFarClasses log2(1/kRhoFar) / log2(dist/hs)) with a small upward margin; a huge
+    // ratio (hs = 0 included) gives log2 = inf and class 1
+    const float lx = log2f((float)(dist / hs));
+    const float q = (float)(kFarClasses * kLog2InvRhoFar) * 1.00001f / lx;
+    const int j = (int)ceilf(q);
+    return j < 1 ? 1 : (j > kFarClasses ? kFarClasses : j);
+}
+
+C0_HD double fmaT(double a, double b, double c) { return fma(a, b, c); }
+C0_HD float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Horner sum over the first cls * K / kFarClasses coefficients (highest first), without the
+// final factor t: sum_{m < n} a[m] t^m.  Class 0 gives 0.  cls is uniform over the wave in the
+// kernels, so every block test is a scalar branch.
+template <int K, class T>
+C0_HD T far_horner_cls(const T *a, T t, int cls)
+{
+    constexpr int S = K / kFarClasses;
+    static_assert(S * kFarClasses == K, "term count must be a multiple of the class count");
+    T s = T(0);
+#pragma unroll
+    for (int j = kFarClasses; j >= 1; --j) {
+        if (j <= cls) {
+#pragma unroll
+            for (int m = j * S - 1; m >= (j - 1) * S; --m) s = fmaT(s, t, a[m]);
+        }
+    }
+    return s;
 }
 
 // h^(n)/n! (x-derivatives of h(x) = u^3 L, u = w - x, L = Log(u + i0)) for n <= 3.

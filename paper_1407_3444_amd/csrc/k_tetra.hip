@@ -35,6 +35,9 @@ constexpr int kQCap = 48;       // near-branch work items queued per lane
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W at the same corners
+    double c, hs;               // centre and half-span of the D values (prep pass)
+    int32_t cls;                // far-series class against the frequency interval (prep pass)
+    int32_t allfar;             // 1: no frequency of the interval is near (prep pass)
     union {
         alignas(16) double a[kFarTerms];     // far-branch series coefficients (FP64 form)
         alignas(16) float a32[kFarTerms32];  // the same series, first kFarTerms32 terms (mixed form)
@@ -199,6 +202,20 @@ __device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, int64_
     return nrec;
 }
 
+__device__ __forceinline__ double wave_min(double x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmin(x, __shfl_xor(x, d, kWave));
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, kWave));
+    return x;
+}
+
 // 1/d to full FP64 precision: hardware reciprocal estimate + two Newton steps
 __device__ __forceinline__ double recip(double d)
 {
@@ -206,6 +223,33 @@ __device__ __forceinline__ double recip(double d)
     t = fma(t, fma(-d, t, 1.0), t);
     t = fma(t, fma(-d, t, 1.0), t);
     return t;
+}
+
+// 1/d in FP32: hardware estimate + one Newton step
+__device__ __forceinline__ float recip32(float d)
+{
+    const float t = __builtin_amdgcn_rcpf(d);
+    return fmaf(t, fmaf(-d, t, 1.0f), t);
+}
+
+// NSLOT independent Horner chains sum_{m < n} a[m] t_s^m over the first n = cls K / kFarClasses
+// coefficients (cls wave-uniform: one scalar branch per block of terms).
+template <int K, int NSLOT, class T>
+__device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T *f)
+{
+    constexpr int S = K / kFarClasses;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) f[s] = T(0);
+#pragma unroll
+    for (int j = kFarClasses; j >= 1; --j) {
+        if (j <= cls) {
+#pragma unroll
+            for (int m = j * S - 1; m >= (j - 1) * S; --m) {
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) f[s] = fmaT(f[s], tt[s], a[m]);
+            }
+        }
+    }
 }
 
 // Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.
@@ -246,17 +290,24 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     const int lane = threadIdx.x;
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
 
-    // frequencies of this lane (slot s holds w[lane + 64 s]) and each slot's range over the wave
+    // frequencies of this lane (slot s holds w[lane + 64 s]; dead lanes repeat the last one)
+    // and their interval [wlo, whi] over the wave, from which each tetrahedron's far-series
+    // class follows
     double om[NSLOT];
     bool live[NSLOT];
     cplx acc[NSLOT];
+    double wlo = omega[nw - 1], whi = wlo;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
         const int idx = lane + kWave * s;
         live[s] = idx < nw;
         om[s] = omega[live[s] ? idx : nw - 1];
         acc[s] = cmk(0.0, 0.0);
+        wlo = fmin(wlo, om[s]);
+        whi = fmax(whi, om[s]);
     }
+    wlo = wave_min(wlo);
+    whi = wave_max(whi);
     int qn = 0;
 
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
@@ -282,25 +333,38 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
                 double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
                 sort4(y, w);
+                const double c = 0.5 * (y[0] + y[3]), hs = 0.5 * (y[3] - y[0]);
+                const double dist = fmax(fmax(wlo - c, c - whi), 0.0);
                 if (MIXED) {
                     double a[kFarTerms32];
-                    far_coeffs<kFarTerms32>(y, w, 0.5 * (y[0] + y[3]), a);
+                    far_coeffs<kFarTerms32>(y, w, c, a);
 #pragma unroll
                     for (int m = 0; m < kFarTerms32; ++m) list[r].a32[m] = (float)a[m];
                 } else {
-                    far_coeffs(y, w, 0.5 * (y[0] + y[3]), list[r].a);
+                    far_coeffs(y, w, c, list[r].a);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
+                list[r].c = c;
+                list[r].hs = hs;
+                list[r].cls = far_class(hs, dist, fmax(fabs(wlo - c), fabs(whi - c)));
+                list[r].allfar = hs < kRhoFar * dist ? 1 : 0;
             }
             __syncthreads();
             for (int r = 0; r < nrec; ++r) {
-                // all slots at once: 8 independent Horner chains in the far series; the
-                // coefficients are read from LDS (broadcast) into registers in one burst
-                const double y0 = list[r].y[0], y3 = list[r].y[3];
-                const double c = 0.5 * (y0 + y3), hs = 0.5 * (y3 - y0);
+                // far branch: all slots at once, 8 independent Horner chains on coefficients
+                // read from LDS (broadcast) into registers; the series is cut to the terms the
+                // distance between this tetrahedron and the frequency interval needs (a
+                // wave-uniform class, so the cut is a scalar branch per block of terms).  When
+                // the whole interval is far from the tetrahedron no frequency can take the near
+                // branch, and the per-frequency tests are skipped.
+                const double c = list[r].c, hs = list[r].hs;
+                const int cls = __builtin_amdgcn_readfirstlane(list[r].cls);
+                const bool allfar = __builtin_amdgcn_readfirstlane(list[r].allfar) != 0;
                 bool nearb[NSLOT];
-                if (MIXED) {
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) nearb[s] = allfar ? false : !(hs <= kRhoFar * fabs(om[s] - c));
+                if (cls != 0 && MIXED) {
                     float a[kFarTerms32];
 #pragma unroll
                     for (int m = 0; m < kFarTerms32; m += 4) {
@@ -308,25 +372,21 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                         a[m] = v.x; a[m + 1] = v.y; a[m + 2] = v.z; a[m + 3] = v.w;
                     }
                     float tt[NSLOT], f[NSLOT];
+                    if (allfar) {
 #pragma unroll
-                    for (int s = 0; s < NSLOT; ++s) {
-                        const double d = om[s] - c;          // the difference in FP64, then FP32
-                        nearb[s] = !(hs <= kRhoFar * fabs(d));
-                        const float df = (float)(nearb[s] ? 1.0 : d);
-                        float t = __builtin_amdgcn_rcpf(df);
-                        t = fmaf(t, fmaf(-df, t, 1.0f), t);
-                        tt[s] = t;
-                        f[s] = a[kFarTerms32 - 1];
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip32((float)(om[s] - c));
+                        horner_slots<kFarTerms32, NSLOT>(a, tt, cls, f);
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) acc[s].re += (double)(f[s] * tt[s]);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip32((float)(nearb[s] ? 1.0 : om[s] - c));
+                        horner_slots<kFarTerms32, NSLOT>(a, tt, cls, f);
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s)
+                            if (!nearb[s]) acc[s].re += (double)(f[s] * tt[s]);
                     }
-#pragma unroll
-                    for (int m = kFarTerms32 - 2; m >= 0; --m) {
-#pragma unroll
-                        for (int s = 0; s < NSLOT; ++s) f[s] = fmaf(f[s], tt[s], a[m]);
-                    }
-#pragma unroll
-                    for (int s = 0; s < NSLOT; ++s)
-                        if (!nearb[s]) acc[s].re += (double)(f[s] * tt[s]);
-                } else {
+                } else if (cls != 0) {
                     double a[kFarTerms];
 #pragma unroll
                     for (int m = 0; m < kFarTerms; m += 2) {
@@ -335,30 +395,31 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                         a[m + 1] = v.y;
                     }
                     double tt[NSLOT], f[NSLOT];
+                    if (allfar) {
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip(om[s] - c);
+                        horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) acc[s].re = fma(f[s], tt[s], acc[s].re);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip(nearb[s] ? 1.0 : om[s] - c);
+                        horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
+#pragma unroll
+                        for (int s = 0; s < NSLOT; ++s)
+                            if (!nearb[s]) acc[s].re = fma(f[s], tt[s], acc[s].re);
+                    }
+                }
+                if (!allfar) {
 #pragma unroll
                     for (int s = 0; s < NSLOT; ++s) {
-                        const double d = om[s] - c;
-                        nearb[s] = !(hs <= kRhoFar * fabs(d));
-                        tt[s] = recip(nearb[s] ? 1.0 : d);
-                        f[s] = a[kFarTerms - 1];
+                        if (nearb[s] && live[s]) {
+                            queue[qn][lane] = (uint16_t)((r << 3) | s);
+                            ++qn;
+                        }
                     }
-#pragma unroll
-                    for (int m = kFarTerms - 2; m >= 0; --m) {
-#pragma unroll
-                        for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], a[m]);
-                    }
-#pragma unroll
-                    for (int s = 0; s < NSLOT; ++s)
-                        if (!nearb[s]) acc[s].re = fma(f[s], tt[s], acc[s].re);
+                    if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, om, acc);
                 }
-#pragma unroll
-                for (int s = 0; s < NSLOT; ++s) {
-                    if (nearb[s] && live[s]) {
-                        queue[qn][lane] = (uint16_t)((r << 3) | s);
-                        ++qn;
-                    }
-                }
-                if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, om, acc);
             }
             drain_near<NSLOT>(list, queue, qn, lane, om, acc);
             __syncthreads();
@@ -451,23 +512,30 @@ __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B,
 }
 
 // Work census (diagnostic, untimed): counts, over all units of the batch, the units with
-// a non-empty carved region, the final tetrahedra, and the (final tetrahedron, frequency)
-// evaluations that take the near branch and the far branch of the weight evaluation.
+// a non-empty carved region, the final tetrahedra, the (final tetrahedron, frequency)
+// evaluations that take the near branch and the far branch of the weight evaluation, and the
+// far-series terms those far evaluations use (the series cut to the class of the tetrahedron
+// against the launch's frequency interval, exactly as the dynamic kernel does).  At most
+// kMaxOmegaPerLaunch frequencies per launch.
 struct CensusSink {
     const double *omega;
+    double wlo, whi;           // interval of the launch's frequencies
     int nw;
     int form;
-    unsigned long long n_tet, n_near, n_far;
+    int step;                  // series terms per class
+    unsigned long long n_tet, n_near, n_far, n_terms;
     __device__ void one(const double D0, const double D1, const double D2, const double D3)
     {
         double y[4] = {D0, D1, D2, D3}, w[4] = {0.0, 0.0, 0.0, 0.0};
         sort4(y, w);
         const double c = 0.5 * (y[0] + y[3]), r = 0.5 * (y[3] - y[0]);
+        const int cls = far_class(r, fmax(fmax(wlo - c, c - whi), 0.0), fmax(fabs(wlo - c), fabs(whi - c)));
         unsigned long long nn = 0;
         for (int i = 0; i < nw; ++i) nn += (r <= kRhoFar * fabs(omega[i] - c)) ? 0ull : 1ull;
         n_tet += 1;
         n_near += nn;
         n_far += (unsigned long long)nw - nn;
+        n_terms += ((unsigned long long)nw - nn) * (unsigned long long)(cls * step);
     }
     __device__ void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
     {
@@ -478,16 +546,25 @@ struct CensusSink {
 };
 
 __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, const double *__restrict__ omega, int nw,
+                                                     int step, int first_chunk,
                                                      unsigned long long *__restrict__ counts)
 {
+    double wlo = omega[0], whi = omega[0];
+    for (int i = 1; i < nw; ++i) {
+        wlo = fmin(wlo, omega[i]);
+        whi = fmax(whi, omega[i]);
+    }
     const int qi = blockIdx.y;
     const QDev Q = B.q[qi];
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
     CensusSink cs;
     cs.omega = omega;
+    cs.wlo = wlo;
+    cs.whi = whi;
     cs.nw = nw;
     cs.form = M.form;
-    cs.n_tet = cs.n_near = cs.n_far = 0;
+    cs.step = step;
+    cs.n_tet = cs.n_near = cs.n_far = cs.n_terms = 0;
     unsigned long long active = 0;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -498,10 +575,13 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
         if (M.form == 0 && !region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
         active += cs.n_tet > before ? 1ull : 0ull;
     }
-    atomicAdd(&counts[0], active);
-    atomicAdd(&counts[1], cs.n_tet);
+    if (first_chunk) {
+        atomicAdd(&counts[0], active);
+        atomicAdd(&counts[1], cs.n_tet);
+    }
     atomicAdd(&counts[2], cs.n_near);
     atomicAdd(&counts[3], cs.n_far);
+    atomicAdd(&counts[4], cs.n_terms);
 }
 
 }  // namespace
@@ -537,11 +617,13 @@ hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_it
 }
 
 hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, const double *omega, int nw,
-                         unsigned long long *counts, hipStream_t s)
+                         bool mixed, bool first_chunk, unsigned long long *counts, hipStream_t s)
 {
-    if (nq < 1 || nq > kMaxQBatch || nw < 1) return hipErrorInvalidValue;
+    if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch) return hipErrorInvalidValue;
     dim3 grid(1024, nq), block(256);
-    hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, counts);
+    const int step = (mixed ? kFarTerms32 : kFarTerms) / kFarClasses;
+    hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, step, first_chunk ? 1 : 0,
+                       counts);
     return hipGetLastError();
 }
 

@@ -63,4 +63,46 @@ int hc_unit(const double *a, const double *b, const double *W, double om, int fo
     out[1] = acc.sum.im;
     return acc.npieces;
 }
+
+// One group of n <= 64 frequencies evaluated the way the dynamic kernel evaluates a slot: the
+// group's series class from its frequency interval, the far series cut to that class for far
+// frequencies (FP64, or the FP32 form when fp32 = 1), the near evaluation otherwise.
+// out[2i], out[2i+1] = (re, im) at om[i]; far_out[i] = 1 where the far branch was taken.
+// Returns the class.
+int hc_group(const double *D, const double *Wt, const double *om, int n, int fp32, double *out, int *far_out)
+{
+    double y[4] = {D[0], D[1], D[2], D[3]}, w[4] = {Wt[0], Wt[1], Wt[2], Wt[3]};
+    sort4(y, w);
+    const double c = 0.5 * (y[0] + y[3]), hs = 0.5 * (y[3] - y[0]);
+    double lo = om[0], hi = om[0];
+    for (int i = 1; i < n; ++i) {
+        lo = fmin(lo, om[i]);
+        hi = fmax(hi, om[i]);
+    }
+    const int cls = far_class(hs, fmax(fmax(lo - c, c - hi), 0.0), fmax(fabs(lo - c), fabs(hi - c)));
+    double a[kFarTerms];
+    far_coeffs(y, w, c, a);
+    double a32d[kFarTerms32];
+    far_coeffs<kFarTerms32>(y, w, c, a32d);
+    float a32[kFarTerms32];
+    for (int m = 0; m < kFarTerms32; ++m) a32[m] = (float)a32d[m];
+    for (int i = 0; i < n; ++i) {
+        const double d = om[i] - c;
+        const bool nearb = !(hs <= kRhoFar * fabs(d));
+        far_out[i] = nearb ? 0 : 1;
+        cplx z;
+        if (nearb) {
+            z = near_eval(y, w, om[i]);
+        } else if (fp32) {
+            const float t = 1.0f / (float)d;
+            z = cmk((double)(far_horner_cls<kFarTerms32>(a32, t, cls) * t), 0.0);
+        } else {
+            const double t = 1.0 / d;
+            z = cmk(far_horner_cls<kFarTerms>(a, t, cls) * t, 0.0);
+        }
+        out[2 * i] = z.re;
+        out[2 * i + 1] = z.im;
+    }
+    return cls;
+}
 }

@@ -29,6 +29,8 @@ def hc():
     lib.hc_weight_sum.argtypes = [dp, dp, ctypes.c_double, dp]
     lib.hc_unit.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
     lib.hc_unit.restype = ctypes.c_int
+    lib.hc_group.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
+    lib.hc_group.restype = ctypes.c_int
     return lib
 
 
@@ -125,3 +127,51 @@ def test_carved_unit_matches_oracle(hc, form):
         hc.hc_unit(_p(a), _p(b), _p(Wc), float(w), form, _p(out))
         got = complex(out[0], out[1])
         assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (it, a, b, w, got, ref)
+
+
+def _group_cases():
+    """(D, W, omega group of 64): groups of 64 equally spaced frequencies at every distance from
+    the tetrahedron's values, spans from ties to wide."""
+    rng = np.random.default_rng(23)
+    out = []
+    for _ in range(250):
+        c = rng.uniform(0.0, 2.0)
+        hs = 10 ** rng.uniform(-6, -0.5) if rng.random() < 0.9 else 0.0
+        D = c + hs * rng.uniform(-1, 1, 4)
+        D[rng.integers(4)] = c - hs
+        D[rng.integers(4)] = c + hs
+        width = 10 ** rng.uniform(-2, 0)
+        start = c + rng.choice([-1, 1]) * 10 ** rng.uniform(-3, 1) - (width if rng.random() < 0.5 else 0.0)
+        out.append((D, rng.uniform(0, 1, 4), np.linspace(start, start + width, 64)))
+    return out
+
+
+def _group(hc, D, W, om, fp32):
+    D = np.ascontiguousarray(D, float)
+    W = np.ascontiguousarray(W, float)
+    om = np.ascontiguousarray(om, float)
+    out = np.zeros(2 * len(om))
+    far = (ctypes.c_int * len(om))()
+    cls = hc.hc_group(_p(D), _p(W), _p(om), len(om), int(fp32), _p(out), far)
+    return cls, out[0::2] + 1j * out[1::2], np.array(list(far), dtype=bool)
+
+
+@pytest.mark.parametrize("fp32,bound", [(0, 5e-12), (1, 1e-6)])
+def test_series_cut_per_frequency_group_keeps_accuracy(hc, fp32, bound):
+    """The far series cut to the class of a group of 64 frequencies (the terms the group's
+    distance from the tetrahedron needs) matches the oracle's weights at every frequency."""
+    worst, classes = 0.0, []
+    for D, W, om in _group_cases():
+        cls, got, far = _group(hc, D, W, om, fp32)
+        classes.append(cls)
+        assert (cls == 0) == (not far.any())
+        for i in range(len(om)):
+            J = oracle.weights(D, om[i])
+            ref = np.dot(W, J)
+            scale = np.sum(np.abs(W) * np.abs(J))
+            err = abs(got[i] - ref) / scale
+            worst = max(worst, err)
+            assert err < bound, (D, W, om[i], cls, got[i], ref)
+    # the cases exercise short, intermediate and full series
+    assert min(c for c in classes if c > 0) <= 2 and max(classes) == 10 and 0 in classes
+    print("worst relative error", worst, "classes", np.bincount(classes))
