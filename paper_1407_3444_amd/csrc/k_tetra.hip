@@ -54,20 +54,49 @@ constexpr int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 
 // Corner values of unit u (pair-major, then tetrahedron permutation, then cell).
-__device__ __forceinline__ void load_unit(const MeshDev &M, const QDev &Q, int64_t u, Vtx t[4])
+// A unit = (band pair, tetrahedron of a cell, cell): unit index u = (pair * 6 + perm) * Nk + cell.
+struct UnitIdx {
+    int pair, perm, cell;
+};
+
+// General decomposition of a unit index (64-bit divisions).
+__device__ __forceinline__ UnitIdx decode_unit(const MeshDev &M, int64_t u)
+{
+    UnitIdx x;
+    const int64_t q = u / M.nk;
+    x.cell = (int)(u - q * M.nk);
+    x.pair = (int)(q / 6);
+    x.perm = (int)(q - (int64_t)x.pair * 6);
+    return x;
+}
+
+// Unit base + lane of a round of 64 consecutive units: the round's base is decomposed once
+// (wave-uniform, scalar arithmetic) and every lane carries its offset into the cell index.
+__device__ __forceinline__ UnitIdx round_unit(const MeshDev &M, const UnitIdx &b, int lane)
+{
+    UnitIdx x = b;
+    x.cell += lane;
+    const int nk = (int)M.nk;
+    while (x.cell >= nk) {        // at most once unless the mesh has fewer than 64 points
+        x.cell -= nk;
+        if (++x.perm == 6) {
+            x.perm = 0;
+            ++x.pair;
+        }
+    }
+    return x;
+}
+
+__device__ __forceinline__ void load_unit(const MeshDev &M, const QDev &Q, const UnitIdx &x, Vtx t[4])
 {
     const int64_t nk = M.nk;
-    const int64_t per_pair = 6 * nk;
-    const int pair = (int)(u / per_pair);
-    const int64_t rem = u - (int64_t)pair * per_pair;
-    const int perm = (int)(rem / nk);
-    const int64_t cell = rem - (int64_t)perm * nk;
+    const int pair = x.pair, perm = x.perm;
     const int n = pair / M.nbw, m = pair - n * M.nbw;
     int i[3];
-    i[2] = (int)(cell % M.n3);
-    const int64_t c12 = cell / M.n3;
-    i[1] = (int)(c12 % M.n2);
-    i[0] = (int)(c12 / M.n2);
+    const unsigned c12 = (unsigned)x.cell / (unsigned)M.n3;
+    i[2] = x.cell - (int)(c12 * (unsigned)M.n3);
+    i[0] = (int)(c12 / (unsigned)M.n2);
+    i[1] = (int)c12 - i[0] * M.n2;
     const int nn[3] = {M.n1, M.n2, M.n3};
     const double *ek = M.eps_k + (int64_t)(M.lo + n) * nk;
     const double *ekq = Q.eps_kq + (int64_t)(M.lo + m) * nk;
@@ -183,7 +212,7 @@ __device__ __forceinline__ int wave_inclusive_scan(int x, int lane)
 // The unit's corner values are loaded again here (cache hits) rather than kept in
 // registers across the evaluation of the list.
 template <class Rec, int CAP>
-__device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, int64_t u, bool valid, int cnt,
+__device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, const UnitIdx &ux, bool valid, int cnt,
                                          int start, int lane, Rec *list, int &next_out)
 {
     const int c = (lane >= start) ? cnt : 0;
@@ -195,7 +224,7 @@ __device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, int64_
     const int nrec = __shfl(incl, next - 1, kWave);
     if (fits && valid && cnt > 0) {
         Vtx t[4];
-        load_unit(M, Q, u, t);
+        load_unit(M, Q, ux, t);
         write_unit<Rec>(t, M.form, list, excl, incl);
     }
     next_out = next;
@@ -256,7 +285,7 @@ __device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T
 // Lanes with an empty queue idle; the loop ends when every queue is empty.
 template <int NSLOT>
 __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
-                                           const double *om, cplx *acc)
+                                           const double *__restrict__ omega, cplx *acc)
 {
     while (__any(qn > 0)) {
         if (qn > 0) {
@@ -266,10 +295,9 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
             double y[4], w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
-            double o = om[0];
-#pragma unroll
-            for (int ss = 1; ss < NSLOT; ++ss) o = (s == ss) ? om[ss] : o;
-            const cplx z = near_eval(y, w, o);
+            // the frequency is read again (a cached load) rather than picked out of the
+            // lane's register array, which would be indexed dynamically
+            const cplx z = near_eval(y, w, omega[lane + kWave * s]);
 #pragma unroll
             for (int ss = 0; ss < NSLOT; ++ss) {
                 const bool hit = s == ss;
@@ -313,18 +341,18 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
     // samples all band pairs, so the work per workgroup is even
     for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const int64_t u = base + lane;
-        const bool valid = u < n_units;
+        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
-            load_unit(M, Q, u, t);
+            load_unit(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<DynRec, kCapDyn>(M, Q, u, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<DynRec, kCapDyn>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -418,10 +446,10 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                             ++qn;
                         }
                     }
-                    if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, om, acc);
+                    if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, omega, acc);
                 }
             }
-            drain_near<NSLOT>(list, queue, qn, lane, om, acc);
+            drain_near<NSLOT>(list, queue, qn, lane, omega, acc);
             __syncthreads();
         }
     }
@@ -436,7 +464,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
 }
 
 template <int NSLOT, bool MIXED>
-__global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
                                                            const double *__restrict__ omega, int nw,
                                                            double *__restrict__ partial)
 {
@@ -449,7 +477,7 @@ __global__ __launch_bounds__(64) void tetra_dynamic_kernel(MeshDev M, BatchDev B
 
 // Fused launch over the (instance, q) items of a batch: workgroup -> item from a table, then the
 // item's own frequency count and precision select the instantiation.
-__global__ __launch_bounds__(64) void tetra_batch_kernel(const BatchItemDev *__restrict__ items,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_batch_kernel(const BatchItemDev *__restrict__ items,
                                                          const int32_t *__restrict__ block_item)
 {
     __shared__ DynRec list[kCapDyn];
@@ -483,18 +511,18 @@ __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B,
     const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
     double acc = 0.0;
     for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const int64_t u = base + lane;
-        const bool valid = u < n_units;
+        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
-            load_unit(M, Q, u, t);
+            load_unit(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<StatRec, kCapStat>(M, Q, u, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<StatRec, kCapStat>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -569,7 +597,7 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
          u += (int64_t)gridDim.x * blockDim.x) {
         Vtx t[4];
-        load_unit(M, Q, u, t);
+        load_unit(M, Q, decode_unit(M, u), t);
         const unsigned long long before = cs.n_tet;
         if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, cs);
         if (M.form == 0 && !region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
