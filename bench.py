@@ -35,12 +35,14 @@ sys.path.insert(0, ROOT)
 #        (the census counts the terms each far evaluation uses; a Horner FMA per term beyond
 #        the first, so an n-term series costs 11 + 2 n)
 #   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
-#        three 2-node entries (recursion 16 + 18-term series 181 + test 2: 600), two 3-node
-#        entries (recursion 16 + series 303 + test 2: 642), top entry 12, accumulate 2
+#        three 2-node entries (recursion 16 + 14-term series: complex low orders 61 + 11 real
+#        terms x 8 = 149, test 2: 3 x 167 + 3 = 504), two 3-node entries (recursion 16 + series:
+#        low orders 47 + 12 real terms x 16 = 239, test 2: 2 x 257 = 514), top entry 12,
+#        accumulate 2
 #   prep (per final tetrahedron): 40 far-series coefficients with W-derivatives (23 each) + 6
 FLOPS_FAR_BASE = 11
 FLOPS_PER_TERM = 2
-FLOPS_NEAR = 1388
+FLOPS_NEAR = 1164
 FLOPS_PREP = 926
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 

@@ -41,14 +41,12 @@ constexpr double kPi = 3.14159265358979323846;
 #ifndef CHI0_FAR_TERMS
 #define CHI0_FAR_TERMS 40
 #define CHI0_RHO_FAR 0.4
-#define CHI0_LOG2_INV_RHO_FAR 1.3219280948873623   // log2(1 / CHI0_RHO_FAR)
 #endif
 #ifndef CHI0_THETA_ENTRY
 #define CHI0_THETA_ENTRY 0.1
 #endif
 constexpr int kFarTerms = CHI0_FAR_TERMS;          // series terms kept in the far branch
 constexpr double kRhoFar = CHI0_RHO_FAR;           // far branch when half-span <= kRhoFar * |w - c|
-constexpr double kLog2InvRhoFar = CHI0_LOG2_INV_RHO_FAR;
 constexpr double kThetaEntry = CHI0_THETA_ENTRY;   // series sub-entry when span <= kThetaEntry * |w - x_end|
 // Mixed-precision form: the far series in FP32 with kFarTerms32 terms (0.4^20 ~ 1e-8, the
 // FP32 resolution); near and clustered tetrahedra keep the FP64 evaluation.
@@ -59,6 +57,19 @@ struct cplx {
 };
 
 C0_HD cplx cmk(double r, double i) { cplx z; z.re = r; z.im = i; return z; }
+
+// 1/d: on the GPU the hardware estimate refined by two Newton steps (within an ulp or two of
+// the correctly rounded quotient, without the division's scaling and fix-up sequence)
+C0_HD double rcp(double d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double t = __builtin_amdgcn_rcp(d);
+    t = fma(t, fma(-d, t, 1.0), t);
+    return fma(t, fma(-d, t, 1.0), t);
+#else
+    return 1.0 / d;
+#endif
+}
 C0_HD cplx cadd(cplx a, cplx b) { return cmk(a.re + b.re, a.im + b.im); }
 C0_HD cplx csub(cplx a, cplx b) { return cmk(a.re - b.re, a.im - b.im); }
 C0_HD cplx cscale(cplx a, double s) { return cmk(a.re * s, a.im * s); }
@@ -249,7 +260,7 @@ C0_HD int far_class(double hs, double dist, double dfar)
     // j = ceil(kFarClasses log2(1/kRhoFar) / log2(dist/hs)) with a small upward margin; a huge
     // ratio (hs = 0 included) gives log2 = inf and class 1
     const float lx = log2f((float)(dist / hs));
-    const float q = (float)(kFarClasses * kLog2InvRhoFar) * 1.00001f / lx;
+    const float q = (float)kFarClasses * log2f((float)(1.0 / kRhoFar)) * 1.00001f / lx;
     const int j = (int)ceilf(q);
     return j < 1 ? 1 : (j > kFarClasses ? kFarClasses : j);
 }
@@ -294,14 +305,17 @@ C0_HD cplx hder_low(int n, double u, cplx L)
 // offset of e itself is exactly 0, so H_m only runs over the other P offsets z (with
 // W-derivatives dz) and dH_m gains dz_e H_{m-1}.  Exact to rounding when the nodes lie within
 // kThetaEntry |u| of y_e; computed for every lane (no data-dependent trip count).
-constexpr int kEntryTerms = 18;
+#ifndef CHI0_ENTRY_TERMS
+#define CHI0_ENTRY_TERMS 14
+#endif
+constexpr int kEntryTerms = CHI0_ENTRY_TERMS;
 
 C0_HD double entry_coef(int n) { return 6.0 / ((double)n * (n - 1) * (n - 2) * (n - 3)); }
 
 // P = 1: nodes y_e and y_o.  H_m = z^m, dH_m = z^(m-1) (dz_e + m dz_o).
 C0_HD void taylor_pair(double ye, double we, double yo, double wo, double u, cplx L, cplx &val, cplx &tan)
 {
-    const double inv = 1.0 / u;
+    const double inv = rcp(u);
     const double z = (yo - ye) * inv, dze = we * inv, dzo = wo * inv;
     // m = 0, 1, 2: the first, second and third derivative terms (logarithmic, complex)
     const cplx h1 = hder_low(1, u, L), h2 = hder_low(2, u, L), h3 = hder_low(3, u, L);
@@ -330,7 +344,7 @@ C0_HD void taylor_pair(double ye, double we, double yo, double wo, double u, cpl
 C0_HD void taylor_triple(double ye, double we, double y1, double w1, double y2, double w2, double u, cplx L,
                          cplx &val, cplx &tan)
 {
-    const double inv = 1.0 / u;
+    const double inv = rcp(u);
     const double z1 = (y1 - ye) * inv, z2 = (y2 - ye) * inv;
     const double dze = we * inv, dz1 = w1 * inv, dz2 = w2 * inv;
     double A = 1.0, dA = 0.0, Bv = 1.0, dB = 0.0;      // H_m(z1), H_m(z1, z2) and derivatives
@@ -371,7 +385,7 @@ C0_HD void newton_entry(const double *y, const double *w, const double *u, const
                         cplx B, cplx dB, cplx &V, cplx &T)
 {
     const double span = y[P] - y[0];
-    const double inv = 1.0 / span;
+    const double inv = rcp(span);
     const cplx E = cscale(csub(A, B), inv);
     const double dspan = (w[P] - w[0]) * inv;
     cplx dE = cscale(csub(dA, dB), inv);
@@ -420,7 +434,7 @@ C0_HD cplx near_eval(const double y[4], const double w[4], double om)
     for (int i = 0; i < 2; ++i)
         newton_entry<2>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i]);
     // the top entry spans all nodes; in the near branch its span exceeds its distance to w
-    const double inv = 1.0 / (y[3] - y[0]);
+    const double inv = rcp(y[3] - y[0]);
     const cplx E = cscale(csub(V2[1], V2[0]), inv);
     const double dspan = (w[3] - w[0]) * inv;
     cplx dE = cscale(csub(T2[1], T2[0]), inv);

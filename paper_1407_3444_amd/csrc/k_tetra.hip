@@ -245,14 +245,6 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
-// 1/d to full FP64 precision: hardware reciprocal estimate + two Newton steps
-__device__ __forceinline__ double recip(double d)
-{
-    double t = __builtin_amdgcn_rcp(d);
-    t = fma(t, fma(-d, t, 1.0), t);
-    t = fma(t, fma(-d, t, 1.0), t);
-    return t;
-}
 
 // 1/d in FP32: hardware estimate + one Newton step
 __device__ __forceinline__ float recip32(float d)
@@ -425,13 +417,13 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                     double tt[NSLOT], f[NSLOT];
                     if (allfar) {
 #pragma unroll
-                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip(om[s] - c);
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(om[s] - c);
                         horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s) acc[s].re = fma(f[s], tt[s], acc[s].re);
                     } else {
 #pragma unroll
-                        for (int s = 0; s < NSLOT; ++s) tt[s] = recip(nearb[s] ? 1.0 : om[s] - c);
+                        for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(nearb[s] ? 1.0 : om[s] - c);
                         horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s)
