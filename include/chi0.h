@@ -73,9 +73,11 @@ typedef struct chi0_desc {
                                   1/(w-D+i0) - 1/(w+D+i0)  (equal to form 0 under time reversal) */
     int32_t precision;      /* 0: FP64 everywhere.
                                1: mixed: matrix elements from BF16 MFMA with hi+lo split operands
-                                  and FP32 accumulation; dynamic weights of far-cluster final
-                                  tetrahedra in FP32 (near and clustered ones, and the carving,
-                                  stay FP64); chi0 accumulated in FP64.
+                                  and FP32 accumulation; dynamic weights of final tetrahedra in
+                                  FP32 (far series and near branch), except that near-degenerate
+                                  final tetrahedra (two corner values of e'-e within 1e-6 energy
+                                  units) keep the FP64 near branch; carving, differences of
+                                  energies and the chi0 accumulation stay FP64.
                                2: as 1 with FP16 (low part scaled by 2^11) instead of BF16. */
     int32_t reserved[5];    /* must be zero */
     double mu;              /* Fermi level (energy units of the band arrays) */

@@ -287,158 +287,237 @@ C0_HD T far_horner_cls(const T *a, T t, int cls)
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Near branch, in FP64 or (mixed form) FP32.  Node values, weights and frequency come in as
+// FP64; differences of them (u = w - y_i, spans, offsets) are formed in FP64 and only then
+// rounded to the working type T, so no difference is taken in T.
+// ---------------------------------------------------------------------------
+template <class T>
+struct cx {
+    T re, im;
+};
+
+template <class T> C0_HD cx<T> cxm(T r, T i) { cx<T> z; z.re = r; z.im = i; return z; }
+template <class T> C0_HD cx<T> cxsub(cx<T> a, cx<T> b) { return cxm<T>(a.re - b.re, a.im - b.im); }
+template <class T> C0_HD cx<T> cxscale(cx<T> a, T s) { return cxm<T>(a.re * s, a.im * s); }
+template <class T> C0_HD cx<T> cxfma(cx<T> acc, cx<T> a, T s) { return cxm<T>(fmaT(a.re, s, acc.re), fmaT(a.im, s, acc.im)); }
+template <class T> C0_HD cx<T> cxsel(bool c, cx<T> a, cx<T> b) { return cxm<T>(c ? a.re : b.re, c ? a.im : b.im); }
+
+C0_HD double logT(double x) { return log(x); }
+C0_HD float logT(float x) { return logf(x); }
+C0_HD double absT(double x) { return fabs(x); }
+C0_HD float absT(float x) { return fabsf(x); }
+C0_HD float rcp(float d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float t = __builtin_amdgcn_rcpf(d);
+    return fmaf(t, fmaf(-d, t, 1.0f), t);
+#else
+    return 1.0f / d;
+#endif
+}
+
+// Entry series: kEntryTerms terms in FP64; in FP32 the series is selected up to the wider
+// kThetaEntry32 (so the Newton recursion loses at most a factor 1/kThetaEntry32 per level) and
+// needs kEntryTerms32 terms for the FP32 resolution.
+#ifndef CHI0_ENTRY_TERMS
+#define CHI0_ENTRY_TERMS 14
+#endif
+#ifndef CHI0_ENTRY_TERMS32
+#define CHI0_ENTRY_TERMS32 10
+#endif
+#ifndef CHI0_THETA_ENTRY32
+#define CHI0_THETA_ENTRY32 0.3
+#endif
+constexpr int kEntryTerms = CHI0_ENTRY_TERMS;
+constexpr int kEntryTerms32 = CHI0_ENTRY_TERMS32;
+constexpr double kThetaEntry32 = CHI0_THETA_ENTRY32;
+
+template <class T> struct NearParams;
+template <> struct NearParams<double> {
+    static constexpr int terms = kEntryTerms;
+    static constexpr double theta = kThetaEntry;
+};
+template <> struct NearParams<float> {
+    static constexpr int terms = kEntryTerms32;
+    static constexpr double theta = kThetaEntry32;
+};
+
+C0_HD double entry_coef(int n) { return 6.0 / ((double)n * (n - 1) * (n - 2) * (n - 3)); }
+
 // h^(n)/n! (x-derivatives of h(x) = u^3 L, u = w - x, L = Log(u + i0)) for n <= 3.
-C0_HD cplx hder_low(int n, double u, cplx L)
+template <class T>
+C0_HD cx<T> hder_low(int n, T u, cx<T> L)
 {
     switch (n) {
-    case 0: { double u3 = u * u * u; return cmk(u3 * L.re, u3 * L.im); }
-    case 1: { double u2 = u * u; return cmk(-(3.0 * u2 * L.re + u2), -3.0 * u2 * L.im); }
-    case 2: return cmk(3.0 * u * L.re + 2.5 * u, 3.0 * u * L.im);
-    default: return cmk(-(L.re + 11.0 / 6.0), -L.im);
+    case 0: { T u3 = u * u * u; return cxm<T>(u3 * L.re, u3 * L.im); }
+    case 1: { T u2 = u * u; return cxm<T>(-(T(3) * u2 * L.re + u2), -T(3) * u2 * L.im); }
+    case 2: return cxm<T>(T(3) * u * L.re + T(2.5) * u, T(3) * u * L.im);
+    default: return cxm<T>(-(L.re + T(11.0 / 6.0)), -L.im);
     }
 }
 
 // Value and W-derivative of a divided difference of h over P+1 nodes (P = 1, 2) as a
-// Taylor series of kEntryTerms terms about one of its nodes, e (u = w - y_e, L = Log(u)):
+// Taylor series about one of its nodes, e (u = w - y_e, L = Log(u)):
 //   h[..] = sum_m h^(P+m)(y_e)/(P+m)! H_m(y - y_e),
 // H_m the complete homogeneous symmetric polynomial of the offsets, scaled by 1/u.  The
 // offset of e itself is exactly 0, so H_m only runs over the other P offsets z (with
 // W-derivatives dz) and dH_m gains dz_e H_{m-1}.  Exact to rounding when the nodes lie within
-// kThetaEntry |u| of y_e; computed for every lane (no data-dependent trip count).
-#ifndef CHI0_ENTRY_TERMS
-#define CHI0_ENTRY_TERMS 14
-#endif
-constexpr int kEntryTerms = CHI0_ENTRY_TERMS;
+// theta |u| of y_e; computed for every lane (no data-dependent trip count).
 
-C0_HD double entry_coef(int n) { return 6.0 / ((double)n * (n - 1) * (n - 2) * (n - 3)); }
-
-// P = 1: nodes y_e and y_o.  H_m = z^m, dH_m = z^(m-1) (dz_e + m dz_o).
-C0_HD void taylor_pair(double ye, double we, double yo, double wo, double u, cplx L, cplx &val, cplx &tan)
+// P = 1: nodes y_e and y_o (offset yo_ye = y_o - y_e).  H_m = z^m, dH_m = z^(m-1) (dz_e + m dz_o).
+template <class T>
+C0_HD void taylor_pair(T yo_ye, T we, T wo, T u, cx<T> L, cx<T> &val, cx<T> &tan)
 {
-    const double inv = rcp(u);
-    const double z = (yo - ye) * inv, dze = we * inv, dzo = wo * inv;
+    const T inv = rcp(u);
+    const T z = yo_ye * inv, dze = we * inv, dzo = wo * inv;
     // m = 0, 1, 2: the first, second and third derivative terms (logarithmic, complex)
-    const cplx h1 = hder_low(1, u, L), h2 = hder_low(2, u, L), h3 = hder_low(3, u, L);
+    const cx<T> h1 = hder_low<T>(1, u, L), h2 = hder_low<T>(2, u, L), h3 = hder_low<T>(3, u, L);
     val = h1;
-    tan = cmk(0.0, 0.0);
-    val = cfma(val, h2, u * z);
-    tan = cfma(tan, h2, u * (dze + dzo));
-    val = cfma(val, h3, u * u * z * z);
-    tan = cfma(tan, h3, u * u * z * (dze + 2.0 * dzo));
+    tan = cxm<T>(T(0), T(0));
+    val = cxfma(val, h2, u * z);
+    tan = cxfma(tan, h2, u * (dze + dzo));
+    val = cxfma(val, h3, u * u * z * z);
+    tan = cxfma(tan, h3, u * u * z * (dze + T(2) * dzo));
     // m >= 3: real coefficients 6/(n(n-1)(n-2)(n-3)) u^2, n = m + 1
-    double zprev = z * z, sv = 0.0, st = 0.0;
+    T zprev = z * z, sv = T(0), st = T(0);
 #pragma unroll
-    for (int m = 3; m < kEntryTerms; ++m) {
-        const double zm = zprev * z;
-        const double cf = entry_coef(m + 1);
-        sv = fma(cf, zm, sv);
-        st = fma(cf * zprev, fma((double)m, dzo, dze), st);
+    for (int m = 3; m < NearParams<T>::terms; ++m) {
+        const T zm = zprev * z;
+        const T cf = T(entry_coef(m + 1));
+        sv = fmaT(cf, zm, sv);
+        st = fmaT(cf * zprev, fmaT(T(m), dzo, dze), st);
         zprev = zm;
     }
-    const double u2 = u * u;
-    val.re = fma(sv, u2, val.re);
-    tan.re = fma(st, u2, tan.re);
+    const T u2 = u * u;
+    val.re = fmaT(sv, u2, val.re);
+    tan.re = fmaT(st, u2, tan.re);
 }
 
-// P = 2: nodes y_e, y_1, y_2.  H_m = H_m(z1, z2) by the recurrence over the two offsets.
-C0_HD void taylor_triple(double ye, double we, double y1, double w1, double y2, double w2, double u, cplx L,
-                         cplx &val, cplx &tan)
+// P = 2: nodes y_e, y_1, y_2 (offsets from y_e).  H_m = H_m(z1, z2) by the recurrence over the
+// two offsets.
+template <class T>
+C0_HD void taylor_triple(T y1_ye, T y2_ye, T we, T w1, T w2, T u, cx<T> L, cx<T> &val, cx<T> &tan)
 {
-    const double inv = rcp(u);
-    const double z1 = (y1 - ye) * inv, z2 = (y2 - ye) * inv;
-    const double dze = we * inv, dz1 = w1 * inv, dz2 = w2 * inv;
-    double A = 1.0, dA = 0.0, Bv = 1.0, dB = 0.0;      // H_m(z1), H_m(z1, z2) and derivatives
+    const T inv = rcp(u);
+    const T z1 = y1_ye * inv, z2 = y2_ye * inv;
+    const T dze = we * inv, dz1 = w1 * inv, dz2 = w2 * inv;
+    T A = T(1), dA = T(0), Bv = T(1), dB = T(0);      // H_m(z1), H_m(z1, z2) and derivatives
     // m = 0, 1: the second and third derivative terms (logarithmic, complex)
-    const cplx h2 = hder_low(2, u, L), h3 = hder_low(3, u, L);
+    const cx<T> h2 = hder_low<T>(2, u, L), h3 = hder_low<T>(3, u, L);
     val = h2;
-    tan = cmk(0.0, 0.0);
+    tan = cxm<T>(T(0), T(0));
     {
-        const double nA = A * z1, ndA = dz1 * A + z1 * dA;
-        const double nB = fma(z2, Bv, nA), ndB = fma(dz2, Bv, fma(z2, dB, ndA));
-        const double dH = fma(dze, Bv, ndB);
-        val = cfma(val, h3, u * nB);
-        tan = cfma(tan, h3, u * dH);
+        const T nA = A * z1, ndA = dz1 * A + z1 * dA;
+        const T nB = fmaT(z2, Bv, nA), ndB = fmaT(dz2, Bv, fmaT(z2, dB, ndA));
+        const T dH = fmaT(dze, Bv, ndB);
+        val = cxfma(val, h3, u * nB);
+        tan = cxfma(tan, h3, u * dH);
         A = nA; dA = ndA; Bv = nB; dB = ndB;
     }
-    double sv = 0.0, st = 0.0;
+    T sv = T(0), st = T(0);
 #pragma unroll
-    for (int m = 2; m < kEntryTerms; ++m) {
-        const double nA = A * z1, ndA = fma(dz1, A, z1 * dA);
-        const double nB = fma(z2, Bv, nA), ndB = fma(dz2, Bv, fma(z2, dB, ndA));
-        const double dH = fma(dze, Bv, ndB);
-        const double cf = entry_coef(m + 2);
-        sv = fma(cf, nB, sv);
-        st = fma(cf, dH, st);
+    for (int m = 2; m < NearParams<T>::terms; ++m) {
+        const T nA = A * z1, ndA = fmaT(dz1, A, z1 * dA);
+        const T nB = fmaT(z2, Bv, nA), ndB = fmaT(dz2, Bv, fmaT(z2, dB, ndA));
+        const T dH = fmaT(dze, Bv, ndB);
+        const T cf = T(entry_coef(m + 2));
+        sv = fmaT(cf, nB, sv);
+        st = fmaT(cf, dH, st);
         A = nA; dA = ndA; Bv = nB; dB = ndB;
     }
-    val.re = fma(sv, u, val.re);
-    tan.re = fma(st, u, tan.re);
+    val.re = fmaT(sv, u, val.re);
+    tan.re = fmaT(st, u, tan.re);
 }
-
-C0_HD cplx csel(bool c, cplx a, cplx b) { return cmk(c ? a.re : b.re, c ? a.im : b.im); }
 
 // One Newton entry over nodes y[0..P] (P = 1, 2) from its two children A = [y_1..y_P] and
-// B = [y_0..y_{P-1}], or, when its nodes cluster within kThetaEntry of their distance to w,
-// from the Taylor series about its end node farther from w.
-template <int P>
-C0_HD void newton_entry(const double *y, const double *w, const double *u, const cplx *L, cplx A, cplx dA,
-                        cplx B, cplx dB, cplx &V, cplx &T)
+// B = [y_0..y_{P-1}], or, when its nodes cluster within theta of their distance to w, from the
+// Taylor series about its end node farther from w.  y: FP64 node values; u: w - y in T.
+template <int P, class T>
+C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L, cx<T> A, cx<T> dA, cx<T> B,
+                        cx<T> dB, cx<T> &V, cx<T> &Tg)
 {
-    const double span = y[P] - y[0];
-    const double inv = rcp(span);
-    const cplx E = cscale(csub(A, B), inv);
-    const double dspan = (w[P] - w[0]) * inv;
-    cplx dE = cscale(csub(dA, dB), inv);
-    dE = cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
-    const double d0 = fabs(u[0]), dP = fabs(u[P]);
+    const T span = T(y[P] - y[0]);
+    const T inv = rcp(span);
+    const cx<T> E = cxscale(cxsub(A, B), inv);
+    const T dspan = (w[P] - w[0]) * inv;
+    cx<T> dE = cxscale(cxsub(dA, dB), inv);
+    dE = cxm<T>(fmaT(-E.re, dspan, dE.re), fmaT(-E.im, dspan, dE.im));
+    const T d0 = absT(u[0]), dP = absT(u[P]);
     const bool first = d0 >= dP;
-    const double far = first ? d0 : dP;
-    const bool use_series = span <= kThetaEntry * far;
-    const bool at_w = far == 0.0;                 // every node at w: h[..] and its derivative vanish
-    const double ue = at_w ? 1.0 : (first ? u[0] : u[P]);
-    const cplx Le = csel(first, L[0], L[P]);
-    cplx Vt, Tt;
+    const T far = first ? d0 : dP;
+    const bool use_series = span <= T(NearParams<T>::theta) * far;
+    const bool at_w = far == T(0);                 // every node at w: h[..] and its derivative vanish
+    const T ue = at_w ? T(1) : (first ? u[0] : u[P]);
+    const cx<T> Le = cxsel(first, L[0], L[P]);
+    cx<T> Vt, Tt;
     if (P == 1) {
-        taylor_pair(first ? y[0] : y[1], first ? w[0] : w[1], first ? y[1] : y[0], first ? w[1] : w[0], ue, Le, Vt,
-                    Tt);
+        taylor_pair<T>(T(first ? y[1] - y[0] : y[0] - y[1]), first ? w[0] : w[1], first ? w[1] : w[0], ue, Le, Vt,
+                       Tt);
     } else {
         // expansion node y[0] or y[2]; the other two in order
-        taylor_triple(first ? y[0] : y[P], first ? w[0] : w[P], first ? y[1] : y[0], first ? w[1] : w[0],
-                      first ? y[P] : y[1], first ? w[P] : w[1], ue, Le, Vt, Tt);
+        const double ye = first ? y[0] : y[P];
+        taylor_triple<T>(T((first ? y[1] : y[0]) - ye), T((first ? y[P] : y[1]) - ye), first ? w[0] : w[P],
+                         first ? w[1] : w[0], first ? w[P] : w[1], ue, Le, Vt, Tt);
     }
-    if (at_w) { Vt = cmk(0.0, 0.0); Tt = cmk(0.0, 0.0); }
-    V = csel(use_series, Vt, E);
-    T = csel(use_series, Tt, dE);
+    if (at_w) { Vt = cxm<T>(T(0), T(0)); Tt = cxm<T>(T(0), T(0)); }
+    V = cxsel(use_series, Vt, E);
+    Tg = cxsel(use_series, Tt, dE);
 }
 
 // Near branch: sum_j W_j J_j at frequency om for sorted nodes y with weights w, as the
 // W-derivative of the Newton table of h over the 4 nodes (leaves from 4 logarithms).
-C0_HD cplx near_eval(const double y[4], const double w[4], double om)
+// h is taken with Log(u) - log(s), s the span of the nodes: the dropped part log(s) u^3 is a
+// cubic, whose third divided difference is a constant, so the W-derivative is unchanged while
+// the logarithms stay O(1) (no cancellation of a large common log(s) between the leaves).
+template <class T>
+C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om)
 {
-    double u[4];
-    cplx L[4], V0[4], T0[4];
+    T u[4], w[4];
+    cx<T> L[4], V0[4], T0[4];
+    const T inv_s = rcp(T(y[3] - y[0]));
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        u[i] = om - y[i];
-        const bool zero = u[i] == 0.0;             // h and h' vanish at u = 0
-        L[i] = cmk(zero ? 0.0 : log(fabs(u[i])), u[i] < 0.0 ? kPi : 0.0);
-        V0[i] = hder_low(0, u[i], L[i]);
-        T0[i] = cscale(hder_low(1, u[i], L[i]), w[i]);
+        u[i] = T(om - y[i]);
+        w[i] = T(wd[i]);
+        const bool zero = u[i] == T(0);             // h and h' vanish at u = 0
+        L[i] = cxm<T>(zero ? T(0) : logT(absT(u[i]) * inv_s), u[i] < T(0) ? T(kPi) : T(0));
+        V0[i] = hder_low<T>(0, u[i], L[i]);
+        T0[i] = cxscale(hder_low<T>(1, u[i], L[i]), w[i]);
     }
-    cplx V1[3], T1[3];
+    cx<T> V1[3], T1[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        newton_entry<1>(y + i, w + i, u + i, L + i, V0[i + 1], T0[i + 1], V0[i], T0[i], V1[i], T1[i]);
-    cplx V2[2], T2[2];
+        newton_entry<1, T>(y + i, w + i, u + i, L + i, V0[i + 1], T0[i + 1], V0[i], T0[i], V1[i], T1[i]);
+    cx<T> V2[2], T2[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-        newton_entry<2>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i]);
+        newton_entry<2, T>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i]);
     // the top entry spans all nodes; in the near branch its span exceeds its distance to w
-    const double inv = rcp(y[3] - y[0]);
-    const cplx E = cscale(csub(V2[1], V2[0]), inv);
-    const double dspan = (w[3] - w[0]) * inv;
-    cplx dE = cscale(csub(T2[1], T2[0]), inv);
-    return cmk(fma(-E.re, dspan, dE.re), fma(-E.im, dspan, dE.im));
+    const T inv = inv_s;
+    const cx<T> E = cxscale(cxsub(V2[1], V2[0]), inv);
+    const T dspan = (w[3] - w[0]) * inv;
+    const cx<T> dE = cxscale(cxsub(T2[1], T2[0]), inv);
+    // for w <= every node all leaves carry the same Im Log = pi (u <= 0), the imaginary part is
+    // the divided difference of a cubic and its W-derivative vanishes: set it exactly (for
+    // w >= every node it is exactly 0 already)
+    const bool below = om <= y[0];
+    return cmk((double)fmaT(-E.re, dspan, dE.re), below ? 0.0 : (double)fmaT(-E.im, dspan, dE.im));
+}
+
+C0_HD cplx near_eval(const double y[4], const double w[4], double om) { return near_eval_t<double>(y, w, om); }
+
+// Mixed form: the near branch in FP32 (see near_eval_t); the kernels keep FP64 for
+// near-degenerate tetrahedra (near_degenerate below).
+C0_HD cplx near_eval32(const double y[4], const double w[4], double om) { return near_eval_t<float>(y, w, om); }
+
+// Mixed form: a final tetrahedron whose sorted corner values have two neighbours closer than
+// tol (or that is flat) keeps the FP64 near branch; kDegenerateTol in the energy unit of the
+// band arrays (eV for the supplied models).
+constexpr double kDegenerateTol = 1e-6;
+C0_HD bool near_degenerate(const double y[4], double tol)
+{
+    return !(y[1] - y[0] >= tol && y[2] - y[1] >= tol && y[3] - y[2] >= tol);
 }
 
 // sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.

@@ -37,7 +37,8 @@ struct DynRec {
     double w[4];                // sign * volume * W at the same corners
     double c, hs;               // centre and half-span of the D values (prep pass)
     int32_t cls;                // far-series class against the frequency interval (prep pass)
-    int32_t allfar;             // 1: no frequency of the interval is near (prep pass)
+    int32_t flags;              // prep pass: 1 = no frequency of the interval is near,
+                                // 2 = near-degenerate (kept FP64 in the mixed form)
     union {
         alignas(16) double a[kFarTerms];     // far-branch series coefficients (FP64 form)
         alignas(16) float a32[kFarTerms32];  // the same series, first kFarTerms32 terms (mixed form)
@@ -273,23 +274,26 @@ __device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T
     }
 }
 
-// Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.
-// Lanes with an empty queue idle; the loop ends when every queue is empty.
-template <int NSLOT>
+// Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.  Each
+// lane's queue has two ends: items of the FP64 evaluation at the bottom (rows 0, 1, ...), and,
+// in the mixed form, items of the FP32 evaluation at the top (rows kQCap-1, kQCap-2, ...).
+// Lanes with an empty end idle; the loop ends when that end is empty in every lane.
+template <int NSLOT, bool F32>
 __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
                                            const double *__restrict__ omega, cplx *acc)
 {
     while (__any(qn > 0)) {
         if (qn > 0) {
             --qn;
-            const int e = queue[qn][lane];
+            const int e = queue[F32 ? kQCap - 1 - qn : qn][lane];
             const int r = e >> 3, s = e & 7;
             double y[4], w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
             // the frequency is read again (a cached load) rather than picked out of the
             // lane's register array, which would be indexed dynamically
-            const cplx z = near_eval(y, w, omega[lane + kWave * s]);
+            const double o = omega[lane + kWave * s];
+            const cplx z = F32 ? near_eval32(y, w, o) : near_eval(y, w, o);
 #pragma unroll
             for (int ss = 0; ss < NSLOT; ++ss) {
                 const bool hit = s == ss;
@@ -328,7 +332,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     }
     wlo = wave_min(wlo);
     whi = wave_max(whi);
-    int qn = 0;
+    int qn = 0, qn32 = 0;      // this lane's FP64 and FP32 near items queued
 
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
     // samples all band pairs, so the work per workgroup is even
@@ -368,7 +372,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 list[r].c = c;
                 list[r].hs = hs;
                 list[r].cls = far_class(hs, dist, fmax(fabs(wlo - c), fabs(whi - c)));
-                list[r].allfar = hs < kRhoFar * dist ? 1 : 0;
+                list[r].flags = (hs < kRhoFar * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
             }
             __syncthreads();
             for (int r = 0; r < nrec; ++r) {
@@ -380,7 +384,10 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 // branch, and the per-frequency tests are skipped.
                 const double c = list[r].c, hs = list[r].hs;
                 const int cls = __builtin_amdgcn_readfirstlane(list[r].cls);
-                const bool allfar = __builtin_amdgcn_readfirstlane(list[r].allfar) != 0;
+                const int flags = __builtin_amdgcn_readfirstlane(list[r].flags);
+                const bool allfar = (flags & 1) != 0;
+                // mixed form: near items of non-degenerate tetrahedra go to the FP32 end
+                const bool f32 = MIXED && (flags & 2) == 0;
                 bool nearb[NSLOT];
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s) nearb[s] = allfar ? false : !(hs <= kRhoFar * fabs(om[s] - c));
@@ -434,14 +441,23 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
 #pragma unroll
                     for (int s = 0; s < NSLOT; ++s) {
                         if (nearb[s] && live[s]) {
-                            queue[qn][lane] = (uint16_t)((r << 3) | s);
-                            ++qn;
+                            if (f32) {
+                                queue[kQCap - 1 - qn32][lane] = (uint16_t)((r << 3) | s);
+                                ++qn32;
+                            } else {
+                                queue[qn][lane] = (uint16_t)((r << 3) | s);
+                                ++qn;
+                            }
                         }
                     }
-                    if (__any(qn > kQCap - NSLOT)) drain_near<NSLOT>(list, queue, qn, lane, omega, acc);
+                    if (__any(qn + qn32 > kQCap - NSLOT)) {
+                        drain_near<NSLOT, false>(list, queue, qn, lane, omega, acc);
+                        if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
+                    }
                 }
             }
-            drain_near<NSLOT>(list, queue, qn, lane, omega, acc);
+            drain_near<NSLOT, false>(list, queue, qn, lane, omega, acc);
+            if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
             __syncthreads();
         }
     }

@@ -105,4 +105,12 @@ int hc_group(const double *D, const double *Wt, const double *om, int n, int fp3
     }
     return cls;
 }
+
+// The near branch alone on sorted nodes, FP64 (fp32 = 0) or the mixed form's FP32 (fp32 = 1).
+void hc_near(const double *y, const double *w, double om, int fp32, double *out)
+{
+    cplx z = fp32 ? near_eval32(y, w, om) : near_eval(y, w, om);
+    out[0] = z.re;
+    out[1] = z.im;
+}
 }
