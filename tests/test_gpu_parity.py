@@ -234,6 +234,30 @@ def test_dynamic_mixed_precision_error(precision):
         assert err <= 1e-5
 
 
+def test_dynamic_mixed_precision_degenerate_model():
+    """Mixed form on the single-band cubic model (CMA, explicit k+q): its symmetric mesh makes many
+    final tetrahedra with tied or nearly tied corner values, which take the FP64 fallback of the
+    near branch; error against the FP64 oracle <= 1e-5 per q."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    wl = synth.make_workload("sc_cma", nk=(12, 12, 12))
+    wl.qs = [q for q in wl.qs if q.eps_kq is not None][:1] + [
+        synth.model_workload(synth.sc_nn_model(1.0), (12, 12, 12), [np.array([0.21, 0.17, 0.07])],
+                             np.zeros(1), static=True).qs[0]]
+    # (w = 0 is left out: at q = (j/16)(1,1,1) some final tetrahedra have e' - e = 0 on a face)
+    om = np.linspace(0.05, 6.0, 96)
+    dev = torch.device("cuda:0")
+    plan = lib.Chi0Plan(wl.nk, torch.from_numpy(wl.eps_k).to(dev), None, cma=True, precision=1)
+    qs = [lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(dev)) for q in wl.qs]
+    _say("dynamic mixed precision, cubic CMA model")
+    got = plan.dynamic(qs, torch.from_numpy(om).cuda()).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i, omega=om)
+        err = _relerr(got[i], ref)
+        _say(f"q {i}: max rel err {err:.2e}")
+        assert err <= 1e-5
+
+
 @pytest.mark.parametrize("n_keep", [9, 5])
 def test_full_size_bcc_band_windows_sampled(n_keep):
     """The 9-orbital bcc model on the full 48^3 mesh (663,552 tetrahedra), one q of the (010)
