@@ -58,14 +58,15 @@ struct cplx {
 
 C0_HD cplx cmk(double r, double i) { cplx z; z.re = r; z.im = i; return z; }
 
-// 1/d: on the GPU the hardware estimate refined by two Newton steps (within an ulp or two of
-// the correctly rounded quotient, without the division's scaling and fix-up sequence)
+// 1/d: on the GPU the hardware estimate (relative error below 5e-8 on gfx950) refined by one
+// third-order step t (1 + e + e^2), e = 1 - d t, which leaves e^3 < 1e-22: within an ulp or two
+// of the correctly rounded quotient, without the division's scaling and fix-up sequence
 C0_HD double rcp(double d)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    double t = __builtin_amdgcn_rcp(d);
-    t = fma(t, fma(-d, t, 1.0), t);
-    return fma(t, fma(-d, t, 1.0), t);
+    const double t = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, t, 1.0);
+    return fma(t, fma(e, e, e), t);
 #else
     return 1.0 / d;
 #endif
