@@ -41,6 +41,8 @@ def _load():
         lib.chi0_oracle.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, i, dp,
                                     ll, ll, i, dp]
         lib.chi0_oracle.restype = i
+        lib.chi0_oracle_pairs.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, i, dp, i, dp]
+        lib.chi0_oracle_pairs.restype = i
         lib.chi0_oracle_moments.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, dp]
         lib.chi0_oracle_moments.restype = i
         lib.chi0_oracle_weights.argtypes = [dp, d, dp]
@@ -104,6 +106,29 @@ def chi0(wl, q_index: int, omega=None, cells=None, nthreads: int = 0, form: Opti
                     shift=q.shift if q.shift is not None else (0, 0, 0), mu=wl.mu,
                     spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi, cma=wl.cma,
                     form=wl.form if form is None else form, cells=cells, nthreads=nthreads)
+
+
+def chi0_pairs(wl, q_index: int, omega=None, nthreads: int = 0, form: Optional[int] = None) -> np.ndarray:
+    """chi0 resolved by band pair: complex array [nbw][nbw][nw] whose sum over pairs is chi0()."""
+    lib = _load()
+    q = wl.qs[q_index]
+    om = _f64(np.atleast_1d((np.zeros(1) if wl.static else wl.omega) if omega is None else omega))
+    lo, hi = wl.window()
+    nbw = hi - lo
+    eps_k = _f64(wl.eps_k)
+    ck = _c128_as_f64(wl.c_k)
+    ekq = _f64(q.eps_kq)
+    ckq = _c128_as_f64(q.c_kq)
+    s = q.shift if q.shift is not None else (0, 0, 0)
+    out = np.zeros((nbw, nbw, om.size, 2))
+    rc = lib.chi0_oracle_pairs(int(wl.nk[0]), int(wl.nk[1]), int(wl.nk[2]), wl.n_bands, wl.n_orb,
+                               _ptr(eps_k), _ptr(ck), _ptr(ekq), _ptr(ckq), int(s[0]), int(s[1]), int(s[2]),
+                               float(wl.mu), float(wl.spin_factor), lo, hi, int(bool(wl.cma)),
+                               int(wl.form if form is None else form), om.size, _ptr(om), int(nthreads),
+                               _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle_pairs failed with code %d" % rc)
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def moments(wl, q_index: int, pmax: int = 6) -> np.ndarray:

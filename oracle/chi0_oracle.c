@@ -393,7 +393,10 @@ static void add_piece(const btet *S, const double Dc[4], const double Wc[4], dou
     }
 }
 
-static void tet_contribution(const problem *P, long long cell, int t, int nw, const double *omega, cplx *acc)
+/* Contributions of one mesh tetrahedron, all band pairs.  Pair (n, m) adds into
+ * acc + (n * nbw + m) * pair_stride (pair_stride = 0: every pair into acc). */
+static void tet_contribution(const problem *P, long long cell, int t, int nw, const double *omega, cplx *acc,
+                             long long pair_stride)
 {
     long long idx[4], idq[4];
     tet_corners(P->n, cell, t, idx);
@@ -410,12 +413,13 @@ static void tet_contribution(const problem *P, long long cell, int t, int nw, co
                 Dc[c] = ep - e;
                 Wc[c] = P->cma ? 1.0 : P->W[((size_t)n * P->nbw + m) * P->nk + idx[c]];
             }
+            cplx *pacc = acc + (size_t)(n * P->nbw + m) * pair_stride;
             btet S[9];
             int ns = carve_region(a, b, 1, S);
-            for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, acc);
+            for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, pacc);
             if (P->form == 0) {
                 ns = carve_region(a, b, 2, S);
-                for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, acc);
+                for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, pacc);
             }
         }
 }
@@ -481,7 +485,7 @@ int chi0_oracle(int n1, int n2, int n3, int nb, int no,
 #pragma omp for schedule(static)
 #endif
         for (long long cell = cell_begin; cell < cell_end; ++cell)
-            for (int t = 0; t < 6; ++t) tet_contribution(&P, cell, t, nw, omega, my);
+            for (int t = 0; t < 6; ++t) tet_contribution(&P, cell, t, nw, omega, my, 0);
     }
     double pref = spin_factor / (6.0 * (double)P.nk);
     for (int iw = 0; iw < nw; ++iw) {
@@ -489,6 +493,55 @@ int chi0_oracle(int n1, int n2, int n3, int nb, int no,
         for (int t = 0; t < nt; ++t) s += acc[(size_t)t * nw + iw];   /* fixed order */
         out[2 * iw] = pref * creal(s);
         out[2 * iw + 1] = pref * cimag(s);
+    }
+    free(acc);
+    free(P.W);
+    return 0;
+}
+
+/*
+ * The same sum resolved by band pair (the band-transition histogram of Sec. III): out
+ * [nbw][nbw][nw][2] receives, for n, m relative to band_lo, the terms of pair (n, m) alone, so
+ * that the sum over all pairs is chi0_oracle's result.  Other arguments as for chi0_oracle.
+ */
+int chi0_oracle_pairs(int n1, int n2, int n3, int nb, int no,
+                      const double *eps_k, const double *c_k,
+                      const double *eps_kq, const double *c_kq,
+                      int s1, int s2, int s3,
+                      double mu, double spin_factor, int band_lo, int band_hi,
+                      int cma, int form, int nw, const double *omega, int nthreads, double *out)
+{
+    problem P;
+    int rc = setup(&P, n1, n2, n3, nb, no, eps_k, c_k, eps_kq, c_kq, s1, s2, s3, mu,
+                   band_lo, band_hi, cma, form);
+    if (rc) return rc;
+    const long long npair = (long long)P.nbw * P.nbw, per = npair * nw;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    cplx *acc = (cplx *)calloc((size_t)nt * per, sizeof(cplx));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        cplx *my = acc + (size_t)tid * per;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (long long cell = 0; cell < P.nk; ++cell)
+            for (int t = 0; t < 6; ++t) tet_contribution(&P, cell, t, nw, omega, my, nw);
+    }
+    double pref = spin_factor / (6.0 * (double)P.nk);
+    for (long long i = 0; i < per; ++i) {
+        cplx s = 0.0;
+        for (int t = 0; t < nt; ++t) s += acc[(size_t)t * per + i];   /* fixed order */
+        out[2 * i] = pref * creal(s);
+        out[2 * i + 1] = pref * cimag(s);
     }
     free(acc);
     free(P.W);

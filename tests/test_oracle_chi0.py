@@ -244,3 +244,44 @@ def test_brute_force_dense_k_sum():
         errs.append(abs(oracle.chi0(wl, 0)[0].real - brute))
     assert errs[1] < errs[0] / 3.0
     assert errs[1] < 2e-3 * abs(brute)
+
+
+def test_band_pair_resolution_sums_to_chi0_and_matches_band_windows():
+    """chi0 resolved by band pair (the band-transition histogram of Sec. III): the pairs sum to
+    the total, every diagonal pair (n, n) equals chi0 over the one-band window [n, n+1), every
+    2x2 block equals chi0 over the two-band window, and every static pair is <= 0 (both carved
+    regions give negative terms at w = 0)."""
+    m = synth.tetragonal_two_site_model(2)
+    wl = synth.model_workload(m, (6, 6, 3), [np.array([0.17, 0.05, 0.11])], np.array([0.0, 0.4, 1.3]))
+    wl.band_lo, wl.band_hi = 2, 8
+    P = oracle.chi0_pairs(wl, 0)
+    tot = oracle.chi0(wl, 0)
+    assert np.max(np.abs(P.sum(axis=(0, 1)) - tot)) <= 1e-13 * np.max(np.abs(tot))
+    for n in range(6):
+        wl1 = synth.model_workload(m, (6, 6, 3), [np.array([0.17, 0.05, 0.11])], wl.omega)
+        wl1.band_lo, wl1.band_hi = 2 + n, 3 + n
+        ref = oracle.chi0(wl1, 0)
+        assert np.max(np.abs(P[n, n] - ref)) <= 1e-13 * max(np.max(np.abs(ref)), 1e-300)
+    wl2 = synth.model_workload(m, (6, 6, 3), [np.array([0.17, 0.05, 0.11])], wl.omega)
+    wl2.band_lo, wl2.band_hi = 4, 6
+    ref = oracle.chi0(wl2, 0)
+    assert np.max(np.abs(P[2:4, 2:4].sum(axis=(0, 1)) - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert np.all(P[:, :, 0].real <= 1e-15)
+
+
+def test_band_pair_orientation_n_at_k_m_at_k_plus_q():
+    """Pair (n, m) takes band n at k and band m at k+q.  With a gapped two-band model (band 0
+    filled, band 1 empty) only transitions 0 -> 1 absorb at w > 0: Im chi0_01 < 0 there while
+    Im chi0_10 vanishes identically (its region e'_0 < mu < e_1 has D = e'_0 - e_1 < 0)."""
+    hop = {}
+    synth._add_pair(hop, (0, 0, 0), np.diag([-1.5, 1.5]))
+    synth._add_pair(hop, (1, 0, 0), np.array([[-0.2, 0.05], [0.05, 0.25]]))
+    synth._add_pair(hop, (0, 1, 0), np.array([[-0.15, 0.0], [0.03, 0.2]]))
+    synth._add_pair(hop, (0, 0, 1), np.array([[-0.1, 0.02], [0.0, 0.15]]))
+    model = synth.TBModel("gapped2", 2, hop)
+    om = np.linspace(0.5, 5.0, 40)
+    wl = synth.model_workload(model, (6, 6, 6), [np.array([0.13, 0.21, 0.07])], om)
+    assert wl.eps_k[0].max() < 0.0 < wl.eps_k[1].min()
+    P = oracle.chi0_pairs(wl, 0)
+    assert np.all(P[1, 0].imag == 0.0) and np.all(P[0, 0] == 0.0) and np.all(P[1, 1] == 0.0)
+    assert P[0, 1].imag.min() < -1e-3 * np.abs(P[0, 1]).max()
