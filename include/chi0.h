@@ -111,6 +111,13 @@ chi0_status chi0_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, size_t
 chi0_status chi0_static(chi0_plan_t plan, int32_t nq, const chi0_q *qs, void *workspace,
                         size_t workspace_bytes, double *chi);
 
+/* Static chi0(q, 0) resolved by band pair (the band-transition histogram of Sec. III, Fig. 8):
+ * chi: device float64 [nq][nbw][nbw]; entry (q, n, m), n and m relative to band_lo, holds the
+ * terms of band n at k and band m at k+q, so the sum over (n, m) is chi0_static's result.
+ * Workspace as for chi0_static (chi0_workspace_size with nw = 1). */
+chi0_status chi0_static_pairs(chi0_plan_t plan, int32_t nq, const chi0_q *qs, void *workspace,
+                              size_t workspace_bytes, double *chi);
+
 /* Dynamic chi0(q, w) on a frequency grid (Sec. IV; Re by the analytic tetrahedron formula,
  * Im by the tetrahedron delta weights, both exact for the linear interpolant).
  * omega: device float64 [nw] (any real values, any order); chi: device float64

@@ -21,7 +21,7 @@ __all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library"
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
-EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
+EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                     "chi0_destroy", "chi0_status_string", "chi0_last_error", "chi0_batch_workspace_size",
                     "chi0_batch_create", "chi0_batch_run", "chi0_batch_tune", "chi0_batch_info_get",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Desc), vp, vp, vp]
     lib.chi0_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     lib.chi0_static.argtypes = [vp, i32, ctypes.POINTER(_Q), vp, sz, vp]
+    lib.chi0_static_pairs.argtypes = [vp, i32, ctypes.POINTER(_Q), vp, sz, vp]
     lib.chi0_dynamic.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
     lib.chi0_matrix_elements.argtypes = [vp, ctypes.POINTER(_Q), vp]
     lib.chi0_profile_enable.argtypes = [vp, i32]
@@ -104,7 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_batch_destroy.argtypes = [vp]
     lib.chi0_batch_last_error.argtypes = [vp]
     lib.chi0_batch_last_error.restype = ctypes.c_char_p
-    for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_dynamic",
+    for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                  "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
                  "chi0_batch_tune", "chi0_batch_info_get", "chi0_batch_destroy"):
@@ -218,6 +219,19 @@ class Chi0Plan:
         st = self._lib.chi0_static(self._h, nq, arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    ctypes.c_void_p(chi.data_ptr()))
         self._check(st, "chi0_static")
+        return chi
+
+    def static_pairs(self, qs: Sequence[Q], workspace=None, out=None):
+        """Re chi0(q, 0) resolved by band pair: float64 tensor [nq, nbw, nbw] (n at k, m at k+q)."""
+        import torch
+        nq = len(qs)
+        ws = workspace if workspace is not None else self.workspace(nq, 1)
+        chi = out if out is not None else torch.empty((nq, self.nbw, self.nbw), dtype=torch.float64,
+                                                      device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_static_pairs(self._h, nq, arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_static_pairs")
         return chi
 
     def dynamic(self, qs: Sequence[Q], omega, workspace=None, out=None):

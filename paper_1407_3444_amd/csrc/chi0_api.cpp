@@ -67,6 +67,13 @@ int n_blocks(const chi0_plan_s *p)
     return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rounds + 3) / 4));
 }
 
+// Workgroups per band pair of the pair-resolved static call: up to 64, each at least 4 rounds.
+int n_blocks_pair(const chi0_plan_s *p)
+{
+    const int64_t rounds = (6 * p->mesh.nk + kWave - 1) / kWave;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(64, (rounds + 3) / 4));
+}
+
 struct Layout {
     size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, count_off, total;
     int qbatch;
@@ -77,7 +84,10 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals)
     Layout L;
     L.qbatch = std::min(nq, kMaxQBatch);
     L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
-    L.part_bytes_per_q = align_up(sizeof(double) * (size_t)n_blocks(p) * nvals);
+    // the partial sums of a dynamic or static call, or of a pair-resolved static call
+    const size_t npairs = (size_t)p->mesh.nbw * p->mesh.nbw;
+    L.part_bytes_per_q = align_up(sizeof(double) * std::max((size_t)n_blocks(p) * nvals,
+                                                           (size_t)n_blocks_pair(p) * npairs));
     L.w_off = 0;
     L.part_off = L.w_bytes_per_q * L.qbatch;
     L.count_off = L.part_off + L.part_bytes_per_q * L.qbatch;
@@ -349,6 +359,37 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
             return device_fail(p, e, "tetrahedron kernel");
         if ((e = timed(p, 2, [&] { return launch_reduce(partial, nqb, nblk, 1, scale, chi + q0, 1, p->stream); })) !=
             hipSuccess)
+            return device_fail(p, e, "reduce kernel");
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_static_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
+    const Layout L = layout(p, nq, 1);
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const int nblk = n_blocks_pair(p);
+    const int npairs = p->mesh.nbw * p->mesh.nbw;
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, L, B);
+        hipError_t e;
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        if ((e = timed(p, 1, [&] { return launch_tetra_static_pairs(p->mesh, B, nqb, nblk, partial, p->stream); })) !=
+            hipSuccess)
+            return device_fail(p, e, "tetrahedron kernel");
+        if ((e = timed(p, 2, [&] {
+                 return launch_reduce(partial, nqb, nblk, npairs, scale, chi + (int64_t)q0 * npairs, npairs, p->stream);
+             })) != hipSuccess)
             return device_fail(p, e, "reduce kernel");
     }
     return CHI0_OK;

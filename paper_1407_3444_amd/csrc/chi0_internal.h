@@ -66,6 +66,10 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
 hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
                                hipStream_t s);
 
+// K_B static resolved by band pair: nblk workgroups per pair, partial sums partial[nq][nblk][nbw^2].
+hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch, int nq, int nblk, double *partial,
+                                     hipStream_t s);
+
 // K_B dynamic: per-block partial sums into partial[nq][nblocks][nw][2], nw <= kMaxOmegaPerLaunch.
 // mixed: far-branch series in FP32 (FP64 near branch and accumulation).
 hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,

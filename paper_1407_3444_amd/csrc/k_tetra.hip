@@ -508,19 +508,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
     }
 }
 
-__global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int nblocks,
-                                                          double *__restrict__ partial)
+// Static evaluation (w = 0, Re only) of units [u0, u1) by workgroup blk of nblocks: rounds of
+// 64 consecutive units dealt round-robin; each lane evaluates its own final tetrahedra.
+// Returns the workgroup's sum (valid in every lane).
+__device__ __forceinline__ double static_body(const MeshDev &M, const QDev &Q, int64_t u0, int64_t u1, int blk,
+                                              int nblocks, StatRec *list)
 {
-    __shared__ StatRec list[kCapStat];
-    const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
-    const int blk = blockIdx.x;
-    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
     double acc = 0.0;
-    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
+    for (int64_t base = u0 + (int64_t)blk * kWave; base < u1; base += (int64_t)nblocks * kWave) {
         const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
-        const bool valid = base + lane < n_units;
+        const bool valid = base + lane < u1;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
@@ -544,7 +542,31 @@ __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B,
     }
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-    if (lane == 0) partial[(int64_t)qi * nblocks + blk] = acc;
+    return acc;
+}
+
+__global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int nblocks,
+                                                          double *__restrict__ partial)
+{
+    __shared__ StatRec list[kCapStat];
+    const int qi = blockIdx.y;
+    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const double acc = static_body(M, B.q[qi], 0, n_units, blockIdx.x, nblocks, list);
+    if (threadIdx.x == 0) partial[(int64_t)qi * nblocks + blockIdx.x] = acc;
+}
+
+// Band-pair resolved static evaluation: workgroup x = p * nblk + j takes the units of pair p
+// (6 Nk consecutive units) as part j of nblk; partial[q][j][pair].
+__global__ __launch_bounds__(64) void tetra_static_pairs_kernel(MeshDev M, BatchDev B, int nblk,
+                                                                double *__restrict__ partial)
+{
+    __shared__ StatRec list[kCapStat];
+    const int qi = blockIdx.y;
+    const int npairs = M.nbw * M.nbw;
+    const int p = blockIdx.x / nblk, j = blockIdx.x - p * nblk;
+    const int64_t per_pair = 6 * M.nk;
+    const double acc = static_body(M, B.q[qi], (int64_t)p * per_pair, (int64_t)(p + 1) * per_pair, j, nblk, list);
+    if (threadIdx.x == 0) partial[((int64_t)qi * nblk + j) * npairs + p] = acc;
 }
 
 // Work census (diagnostic, untimed): counts, over all units of the batch, the units with
@@ -660,6 +682,15 @@ hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, con
     const int step = (mixed ? kFarTerms32 : kFarTerms) / kFarClasses;
     hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, step, first_chunk ? 1 : 0,
                        counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch, int nq, int nblk, double *partial,
+                                     hipStream_t s)
+{
+    if (nq < 1 || nq > kMaxQBatch || nblk < 1) return hipErrorInvalidValue;
+    dim3 grid(nblk * mesh.nbw * mesh.nbw, nq), block(kWave);
+    hipLaunchKernelGGL(tetra_static_pairs_kernel, grid, block, 0, s, mesh, batch, nblk, partial);
     return hipGetLastError();
 }
 

@@ -270,3 +270,25 @@ def test_full_size_bcc_band_windows_sampled(n_keep):
     sample = [37, 290]
     ref = oracle.chi0(wl, 0, omega=wl.omega[sample])
     assert _relerr(got[0][sample], ref) <= TOL, (got[0][sample], ref)
+
+
+@pytest.mark.parametrize("nk,window", [((7, 6, 3), (1, 9)), ((64, 64, 8), (0, 10))])
+def test_static_band_pairs(nk, window):
+    """Static chi0 resolved by band pair against the oracle's pair-resolved sum (every pair,
+    relative to the largest pair of the q) and against chi0_static (sum over pairs); the second
+    case is the full 64x64x8 mesh of the 10-orbital model at the path's M-point neighbourhood."""
+    torch = _torch()
+    qi = [70] if nk[0] == 64 else [0, 3]
+    wl = synth.make_workload("tetra_static", nk=nk, nq=256 if nk[0] == 64 else 8, q_subset=qi)
+    wl.band_lo, wl.band_hi = window
+    plan, qs = _plan(wl)
+    _say("static band pairs", nk, window)
+    got = plan.static_pairs(qs).cpu().numpy()
+    tot = plan.static(qs).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0_pairs(wl, i)[:, :, 0].real
+        scale = np.max(np.abs(ref))
+        err = np.max(np.abs(got[i] - ref)) / scale
+        _say(f"q {i}: max pair error / max pair {err:.2e}")
+        assert err <= TOL
+        assert abs(got[i].sum() - tot[i]) <= 1e-12 * abs(tot[i])
