@@ -49,8 +49,8 @@ FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "e363f65673dff653"
-TRAFFIC_BYTES_PER_LAUNCH = (426465 * 2.0 + 196601 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA = "dad20e53d6983276"
+TRAFFIC_BYTES_PER_LAUNCH = (395698 * 2.0 + 340918 * 1.0) * 1024
 
 
 def census_flops(census: dict) -> int:
