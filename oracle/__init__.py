@@ -131,6 +131,39 @@ def chi0_pairs(wl, q_index: int, omega=None, nthreads: int = 0, form: Optional[i
     return out[..., 0] + 1j * out[..., 1]
 
 
+def kk_tent_matrix(omega, lo: float, hi: float, n_spec: int) -> np.ndarray:
+    """L[i, k] = P int hat_k(w') / (w' - omega_i) dw' for the tents hat_k of the uniform grid
+    w'_k = lo + k h on [lo, hi] (n_spec points), written out from the antiderivative
+    phi(x) = x ln|x| of the integrand: L = [phi(x + h) - 2 phi(x) + phi(x - h)] / h, x = w'_k - omega_i
+    (Sec. II: Re and Im of chi0 are connected by the Kramers-Kronig transformation)."""
+    om = np.atleast_1d(np.asarray(omega, dtype=np.float64))
+    h = (hi - lo) / (n_spec - 1)
+    x = (lo + h * np.arange(n_spec))[None, :] - om[:, None]
+
+    def phi(z):
+        out = np.zeros_like(z)
+        nz = z != 0.0
+        out[nz] = z[nz] * np.log(np.abs(z[nz]))
+        return out
+    direct = (phi(x + h) - 2.0 * phi(x) + phi(x - h)) / h
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = h / x
+        series = np.log1p(-t * t) / t + np.log1p(t) - np.log1p(-t)
+    return np.where(np.abs(x) > 2.0 * h, series, direct)
+
+
+def chi0_kk(wl, q_index: int, omega, n_spec: int, lo: float, hi: float, nthreads: int = 0) -> np.ndarray:
+    """The Kramers-Kronig route: Im chi0 exactly at omega, Re chi0 at omega as the principal-value
+    transform (1/pi) P int Im(w')/(w' - w) dw' of the piecewise-linear interpolant of Im on the
+    uniform grid of n_spec points over [lo, hi] (zero one spacing beyond each end)."""
+    om = np.atleast_1d(np.asarray(omega, dtype=np.float64))
+    grid = lo + (hi - lo) / (n_spec - 1) * np.arange(n_spec)
+    im_grid = chi0(wl, q_index, omega=grid, nthreads=nthreads).imag
+    im_direct = chi0(wl, q_index, omega=om, nthreads=nthreads).imag
+    re = kk_tent_matrix(om, lo, hi, n_spec) @ im_grid / np.pi
+    return re + 1j * im_direct
+
+
 def moments(wl, q_index: int, pmax: int = 6) -> np.ndarray:
     """Exact moments mom[p] of the carved integrand: chi0(w) = sum_p mom[p]/w^(p+1) at large w."""
     lib = _load()

@@ -285,3 +285,39 @@ def test_band_pair_orientation_n_at_k_m_at_k_plus_q():
     P = oracle.chi0_pairs(wl, 0)
     assert np.all(P[1, 0].imag == 0.0) and np.all(P[0, 0] == 0.0) and np.all(P[1, 1] == 0.0)
     assert P[0, 1].imag.min() < -1e-3 * np.abs(P[0, 1]).max()
+
+
+def test_kk_tent_transform_of_the_semicircle():
+    """The discrete principal-value transform of the Kramers-Kronig route against a closed-form
+    Hilbert pair: G(w) = 2 (w - sqrt(w^2 - 1)) has Im G = -2 sqrt(1 - w^2) on |w| < 1 and
+    Re G = 2 w there, 2 (w - sign(w) sqrt(w^2 - 1)) outside; the error falls with the spacing."""
+    om = np.array([-1.7, -0.8, -0.3, 0.0, 0.45, 0.9, 1.3, 2.5])
+    ref = np.where(np.abs(om) < 1, 2 * om, 2 * (om - np.sign(om) * np.sqrt(np.maximum(om * om - 1, 0))))
+    errs = []
+    for n in (201, 801, 3201):
+        grid = np.linspace(-1.0, 1.0, n)
+        im = -2.0 * np.sqrt(np.maximum(1.0 - grid ** 2, 0.0))
+        re = oracle.kk_tent_matrix(om, -1.0, 1.0, n) @ im / np.pi
+        errs.append(np.max(np.abs(re - ref)))
+    assert errs[2] < 2e-3 and errs[2] < errs[1] / 3 < errs[0] / 9
+
+
+def test_kk_route_converges_to_the_analytic_real_part():
+    """Re chi0 from the Kramers-Kronig route on a grid covering the whole spectrum against the
+    analytic Re of the same oracle: the difference is the interpolation error of Im and falls
+    as the spectral grid is refined."""
+    m = synth.tetragonal_two_site_model(2)
+    wl = synth.model_workload(m, (6, 6, 2), [np.array([0.21, 0.08, 0.0])], np.zeros(1))
+    wl.band_lo, wl.band_hi = 3, 7
+    lo, hi = wl.window()
+    e = wl.eps_k[lo:hi]
+    ekq = wl.qs[0].eps_kq[lo:hi]
+    dmin, dmax = ekq.min() - e.max() - 0.05, ekq.max() - e.min() + 0.05
+    om = np.linspace(-0.5, 1.5, 9)
+    exact = oracle.chi0(wl, 0, omega=om)
+    errs = []
+    for n in (400, 1600):
+        kk = oracle.chi0_kk(wl, 0, om, n, dmin, dmax)
+        assert np.max(np.abs(kk.imag - exact.imag)) <= 1e-13 * np.max(np.abs(exact))
+        errs.append(np.max(np.abs(kk.real - exact.real)) / np.max(np.abs(exact.real)))
+    assert errs[1] < 2e-2 and errs[1] < errs[0] / 2
