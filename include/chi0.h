@@ -126,6 +126,20 @@ chi0_status chi0_dynamic(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t
                          const double *omega, void *workspace, size_t workspace_bytes,
                          double *chi);
 
+/* The Kramers-Kronig route (Sec. II: one usually computes Im chi0 only and obtains Re chi0 from it
+ * by the Kramers-Kronig relation, provided the frequencies cover the whole spectrum).
+ * Im chi0 is computed exactly (tetrahedron delta weights, no logarithms) at the requested
+ * frequencies omega (device float64 [nw]) and on the uniform spectral grid
+ * w'_k = spec_lo + k (spec_hi - spec_lo)/(n_spec - 1), k < n_spec; Re chi0 at omega is the exact
+ * principal-value transform (1/pi) P int Im(w')/(w' - w) dw' of the piecewise-linear interpolant
+ * of Im on that grid (taken as zero one spacing beyond each end), so it approximates the analytic
+ * Re to the accuracy of that interpolant: the grid must cover every e' - e of the band window.
+ * chi: device float64 [nq][nw][2] receives (Re, Im).  Workspace: chi0_kk_workspace_size. */
+chi0_status chi0_kk_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, int32_t n_spec, size_t *bytes);
+chi0_status chi0_dynamic_kk(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega,
+                            int32_t n_spec, double spec_lo, double spec_hi, void *workspace,
+                            size_t workspace_bytes, double *chi);
+
 /* Matrix elements of one q, the weights the tetrahedron integration interpolates:
  * W[(n*nbw + m)*Nk + k] = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 (footnote of Sec. III),
  * n, m relative to band_lo, nbw = band_hi - band_lo.  W: device float64 [nbw][nbw][Nk].

@@ -22,6 +22,7 @@ __all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library"
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
 EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
+                    "chi0_kk_workspace_size", "chi0_dynamic_kk",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                     "chi0_destroy", "chi0_status_string", "chi0_last_error", "chi0_batch_workspace_size",
                     "chi0_batch_create", "chi0_batch_run", "chi0_batch_tune", "chi0_batch_info_get",
@@ -85,6 +86,9 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     lib.chi0_static.argtypes = [vp, i32, ctypes.POINTER(_Q), vp, sz, vp]
     lib.chi0_static_pairs.argtypes = [vp, i32, ctypes.POINTER(_Q), vp, sz, vp]
+    lib.chi0_kk_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+    lib.chi0_dynamic_kk.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, i32, ctypes.c_double, ctypes.c_double,
+                                    vp, sz, vp]
     lib.chi0_dynamic.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
     lib.chi0_matrix_elements.argtypes = [vp, ctypes.POINTER(_Q), vp]
     lib.chi0_profile_enable.argtypes = [vp, i32]
@@ -106,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_batch_last_error.argtypes = [vp]
     lib.chi0_batch_last_error.restype = ctypes.c_char_p
     for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
+                 "chi0_kk_workspace_size", "chi0_dynamic_kk",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                  "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
                  "chi0_batch_tune", "chi0_batch_info_get", "chi0_batch_destroy"):
@@ -244,6 +249,25 @@ class Chi0Plan:
         st = self._lib.chi0_dynamic(self._h, nq, arr, nw, _dev_ptr(omega, "torch.float64"),
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(chi.data_ptr()))
         self._check(st, "chi0_dynamic")
+        return torch.view_as_complex(chi)
+
+    def dynamic_kk(self, qs: Sequence[Q], omega, n_spec: int, spec_lo: float, spec_hi: float, workspace=None,
+                   out=None):
+        """chi0(q, w) by the Kramers-Kronig route: Im exact, Re from Im on the uniform spectral grid
+        of n_spec points over [spec_lo, spec_hi]; complex128 tensor [nq, nw]."""
+        import torch
+        nq, nw = len(qs), int(omega.shape[0])
+        if workspace is None:
+            n = ctypes.c_size_t()
+            self._check(self._lib.chi0_kk_workspace_size(self._h, nq, nw, int(n_spec), ctypes.byref(n)),
+                        "chi0_kk_workspace_size")
+            workspace = torch.empty(int(n.value), dtype=torch.uint8, device=self.eps_k.device)
+        chi = out if out is not None else torch.empty((nq, nw, 2), dtype=torch.float64, device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_dynamic_kk(self._h, nq, arr, nw, _dev_ptr(omega, "torch.float64"), int(n_spec),
+                                       float(spec_lo), float(spec_hi), ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel(), ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_dynamic_kk")
         return torch.view_as_complex(chi)
 
     def matrix_elements(self, q: Q, out=None):

@@ -95,6 +95,29 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals)
     return L;
 }
 
+// Workspace of the Kramers-Kronig route: W and the partial sums as for a dynamic call (up to
+// kMaxOmegaIm frequencies per launch), then the frequency list (grid and requested) and the
+// imaginary part on it for one batch of q.
+struct KKLayout {
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, om_off, im_off, total;
+    int qbatch, n_all;
+};
+
+KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
+{
+    KKLayout L;
+    L.qbatch = std::min(nq, kMaxQBatch);
+    L.n_all = K + nw;
+    L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
+    L.part_bytes_per_q = align_up(sizeof(double) * (size_t)n_blocks(p) * 2 * std::min(L.n_all, kMaxOmegaIm));
+    L.w_off = 0;
+    L.part_off = L.w_bytes_per_q * L.qbatch;
+    L.om_off = L.part_off + L.part_bytes_per_q * L.qbatch;
+    L.im_off = L.om_off + align_up(sizeof(double) * (size_t)L.n_all);
+    L.total = L.im_off + align_up(sizeof(double) * 2 * (size_t)L.n_all * L.qbatch);
+    return L;
+}
+
 chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
 {
     if (nq < 1 || !qs) return fail(p, CHI0_E_INVALID_ARG, "nq must be >= 1 and qs non-null");
@@ -431,6 +454,67 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
                  })) != hipSuccess)
                 return device_fail(p, e, "reduce kernel");
         }
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_kk_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, int32_t n_spec, size_t *bytes)
+{
+    if (!p || !bytes) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || nw < 1 || n_spec < 2) return fail(p, CHI0_E_INVALID_ARG, "nq, nw >= 1 and n_spec >= 2 required");
+    if ((int64_t)nw + n_spec > (int64_t)INT32_MAX / 4) return fail(p, CHI0_E_SHAPE, "too many frequencies");
+    *bytes = kk_layout(p, nq, nw, n_spec).total;
+    return CHI0_OK;
+}
+
+chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega,
+                            int32_t n_spec, double spec_lo, double spec_hi, void *ws, size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (nw < 1 || !omega || !chi || n_spec < 2)
+        return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, n_spec >= 2, omega and chi non-null required");
+    if (!std::isfinite(spec_lo) || !std::isfinite(spec_hi)) return fail(p, CHI0_E_NONFINITE, "spectral range");
+    if (!(spec_hi > spec_lo)) return fail(p, CHI0_E_INVALID_ARG, "spec_hi must exceed spec_lo");
+    size_t need = 0;
+    if ((st = chi0_kk_workspace_size(p, nq, nw, n_spec, &need)) != CHI0_OK) return st;
+    const KKLayout L = kk_layout(p, nq, nw, n_spec);
+    if (!ws || ws_bytes < need) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    char *base = static_cast<char *>(ws);
+    double *partial = reinterpret_cast<double *>(base + L.part_off);
+    double *om_all = reinterpret_cast<double *>(base + L.om_off);
+    double *im_all = reinterpret_cast<double *>(base + L.im_off);
+    const double h = (spec_hi - spec_lo) / (double)(n_spec - 1);
+    const int nblk = n_blocks(p);
+    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    hipError_t e = launch_kk_grid(spec_lo, h, n_spec, omega, nw, om_all, p->stream);
+    if (e != hipSuccess) return device_fail(p, e, "frequency grid kernel");
+    Layout Lw = {};   // W of the batch sits at the start of the workspace, as for chi0_dynamic
+    Lw.w_off = L.w_off;
+    Lw.w_bytes_per_q = L.w_bytes_per_q;
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, Lw, B);
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        for (int w0 = 0; w0 < L.n_all; w0 += kMaxOmegaIm) {
+            const int nwc = std::min(kMaxOmegaIm, L.n_all - w0);
+            if ((e = timed(p, 1, [&] {
+                     return launch_tetra_im(p->mesh, B, nqb, nblk, om_all + w0, nwc, partial, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "imaginary-part kernel");
+            if ((e = timed(p, 2, [&] {
+                     return launch_reduce(partial, nqb, nblk, 2 * nwc, scale, im_all + 2 * (int64_t)w0,
+                                          2 * (int64_t)L.n_all, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "reduce kernel");
+        }
+        if ((e = launch_kk_transform(im_all, nqb, n_spec, nw, spec_lo, h, omega, chi + (int64_t)q0 * nw * 2,
+                                     2 * (int64_t)nw, p->stream)) != hipSuccess)
+            return device_fail(p, e, "Kramers-Kronig kernel");
     }
     return CHI0_OK;
 }

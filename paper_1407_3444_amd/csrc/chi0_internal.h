@@ -11,6 +11,7 @@ constexpr int kMaxQBatch = 16;     // q-points handled by one launch of each ker
 constexpr int kWave = 64;
 constexpr int kSlots = 8;          // frequencies per lane in the dynamic kernel (8 x 64 = 512)
 constexpr int kMaxOmegaPerLaunch = kSlots * kWave;
+constexpr int kMaxOmegaIm = 16 * kWave;   // frequencies per launch of the imaginary-part kernel
 
 // Per-q data of one batch.
 struct QDev {
@@ -65,6 +66,20 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
 // K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
 hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
                                hipStream_t s);
+
+// K_B imaginary part alone (delta weights): partial sums partial[nq][nblocks][nw][2] with Re = 0,
+// nw <= kMaxOmegaIm.
+hipError_t launch_tetra_im(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
+                           int nw, double *partial, hipStream_t s);
+
+// Kramers-Kronig route: omega_all[k] = lo + k h (k < K), omega_all[K + i] = omega[i] (i < nw).
+hipError_t launch_kk_grid(double lo, double h, int K, const double *omega, int nw, double *omega_all, hipStream_t s);
+
+// Kramers-Kronig route: out[q][i] = (Re, Im), Re = (1/pi) sum_k im_all[q][k].im L_k(omega_i) over the
+// K grid points (tents of the piecewise-linear interpolant, zero one spacing beyond each end),
+// Im = im_all[q][K + i].im; im_all is [nq][K + nw][2].
+hipError_t launch_kk_transform(const double *im_all, int nq, int K, int nw, double lo, double h, const double *omega,
+                               double *out, int64_t out_stride, hipStream_t s);
 
 // K_B static resolved by band pair: nblk workgroups per pair, partial sums partial[nq][nblk][nbw^2].
 hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch, int nq, int nblk, double *partial,

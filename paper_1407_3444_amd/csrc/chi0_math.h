@@ -512,6 +512,70 @@ C0_HD cplx near_eval(const double y[4], const double w[4], double om) { return n
 // near-degenerate tetrahedra (near_degenerate below).
 C0_HD cplx near_eval32(const double y[4], const double w[4], double om) { return near_eval_t<float>(y, w, om); }
 
+// ---------------------------------------------------------------------------
+// Imaginary part alone (the tetrahedron delta weights, Sec. II, Eq. (2)):
+// Im h(x) = pi (w - x)^3 for x > w and 0 for x <= w, i.e. -pi v^3 [v > 0] with v = x - w.  An
+// entry of the Newton table whose nodes all lie on one side of w is the divided difference of 0 or
+// of the plain cubic -pi v^3, known in closed form; only entries whose nodes straddle w use the
+// recursion, whose span then separates nodes on both sides of w.  No logarithm, no series.
+// Returns Im sum_j W_j J_j for sorted nodes y with weights w at frequency om.
+// ---------------------------------------------------------------------------
+struct RD {
+    double v, t;   // value and W-derivative
+};
+
+template <int P>
+C0_HD RD im_entry_poly(const double *v, const double *w)
+{
+    RD r;
+    if (P == 0) { r.v = -kPi * v[0] * v[0] * v[0]; r.t = -3.0 * kPi * v[0] * v[0] * w[0]; }
+    if (P == 1) {
+        r.v = -kPi * (v[0] * v[0] + v[0] * v[1] + v[1] * v[1]);
+        r.t = -kPi * ((2.0 * v[0] + v[1]) * w[0] + (v[0] + 2.0 * v[1]) * w[1]);
+    }
+    if (P == 2) { r.v = -kPi * (v[0] + v[1] + v[2]); r.t = -kPi * (w[0] + w[1] + w[2]); }
+    if (P == 3) { r.v = -kPi; r.t = 0.0; }
+    return r;
+}
+
+// entry over nodes i..i+P from its children B = [i..i+P-1], A = [i+1..i+P]
+template <int P>
+C0_HD RD im_entry(const double *y, const double *v, const double *w, RD A, RD B)
+{
+    RD r;
+    if (v[P] <= 0.0) {                 // every node at or below w: Im h vanishes on all of them
+        r.v = 0.0;
+        r.t = 0.0;
+    } else if (v[0] >= 0.0) {          // every node at or above w: the plain cubic
+        r = im_entry_poly<P>(v, w);
+    } else {                           // nodes on both sides of w
+        const double inv = rcp(y[P] - y[0]);
+        r.v = (A.v - B.v) * inv;
+        r.t = fma(-r.v, (w[P] - w[0]) * inv, (A.t - B.t) * inv);
+    }
+    return r;
+}
+
+C0_HD double near_im(const double y[4], const double w[4], double om)
+{
+    double v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = y[i] - om;
+    RD L0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const RD z = {0.0, 0.0};
+        L0[i] = im_entry<0>(y + i, v + i, w + i, z, z);
+    }
+    RD L1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L1[i] = im_entry<1>(y + i, v + i, w + i, L0[i + 1], L0[i]);
+    RD L2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) L2[i] = im_entry<2>(y + i, v + i, w + i, L1[i + 1], L1[i]);
+    return im_entry<3>(y, v, w, L2[1], L2[0]).t;
+}
+
 // Mixed form: a final tetrahedron whose sorted corner values have two neighbours closer than
 // tol (or that is flat) keeps the FP64 near branch; kDegenerateTol in the energy unit of the
 // band arrays (eV for the supplied models).

@@ -555,6 +555,116 @@ __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B,
     if (threadIdx.x == 0) partial[(int64_t)qi * nblocks + blockIdx.x] = acc;
 }
 
+// Imaginary part alone (tetrahedron delta weights, for the Kramers-Kronig route): every
+// (final tetrahedron, frequency) pair with the frequency strictly inside the tetrahedron's range
+// of D values is queued and evaluated without logarithms (near_im); outside that range the
+// imaginary part vanishes exactly, so nothing else is evaluated.  Up to 16 slots (1024
+// frequencies) per launch.
+struct ImRec {
+    double y[4];                // D at the corners (sorted ascending after the prep pass)
+    double w[4];                // sign * volume * W
+};
+constexpr int kCapIm = 64;      // final tetrahedra per LDS list
+constexpr int kQCapIm = 64;     // work items queued per lane
+
+template <int NSLOT>
+__device__ __forceinline__ void drain_im(const ImRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
+                                         const double *__restrict__ omega, double *acc)
+{
+    while (__any(qn > 0)) {
+        if (qn > 0) {
+            --qn;
+            const int e = queue[qn][lane];
+            const int r = e >> 5, s = e & 31;
+            double y[4], w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
+            const double v = near_im(y, w, omega[lane + kWave * s]);
+#pragma unroll
+            for (int ss = 0; ss < NSLOT; ++ss) acc[ss] += (s == ss) ? v : 0.0;
+        }
+    }
+}
+
+template <int NSLOT>
+__global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int nblocks,
+                                                      const double *__restrict__ omega, int nw,
+                                                      double *__restrict__ partial)
+{
+    __shared__ ImRec list[kCapIm];
+    __shared__ uint16_t queue[kQCapIm][kWave];
+    const int qi = blockIdx.y;
+    const QDev Q = B.q[qi];
+    const int lane = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    double om[NSLOT], acc[NSLOT];
+    bool live[NSLOT];
+    double wlo = omega[nw - 1], whi = wlo;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int idx = lane + kWave * s;
+        live[s] = idx < nw;
+        om[s] = omega[live[s] ? idx : nw - 1];
+        acc[s] = 0.0;
+        wlo = fmin(wlo, om[s]);
+        whi = fmax(whi, om[s]);
+    }
+    wlo = wave_min(wlo);
+    whi = wave_max(whi);
+    int qn = 0;
+    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
+        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const bool valid = base + lane < n_units;
+        int cnt = 0;
+        if (valid) {
+            Vtx t[4];
+            load_unit(M, Q, ux, t);
+            cnt = count_unit(t, M.form);
+        }
+        int start = 0;
+        while (start < kWave) {
+            int next;
+            const int nrec = fill_list<ImRec, kCapIm>(M, Q, ux, valid, cnt, start, lane, list, next);
+            start = next;
+            if (nrec == 0) continue;
+            __syncthreads();
+            for (int r = lane; r < nrec; r += kWave) {
+                double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
+                double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
+                sort4(y, w);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
+            }
+            __syncthreads();
+            for (int r = 0; r < nrec; ++r) {
+                const double y0 = list[r].y[0], y3 = list[r].y[3];
+                // wave-uniform: the tetrahedron's D range misses every frequency of the launch
+                if (__builtin_amdgcn_readfirstlane(y0 < whi && y3 > wlo ? 1 : 0) == 0) continue;
+#pragma unroll
+                for (int s = 0; s < NSLOT; ++s) {
+                    if (live[s] && y0 < om[s] && om[s] < y3) {
+                        queue[qn][lane] = (uint16_t)((r << 5) | s);
+                        ++qn;
+                    }
+                }
+                if (__any(qn > kQCapIm - NSLOT)) drain_im<NSLOT>(list, queue, qn, lane, omega, acc);
+            }
+            drain_im<NSLOT>(list, queue, qn, lane, omega, acc);
+            __syncthreads();
+        }
+    }
+    double *part = partial + ((int64_t)qi * nblocks + blk) * nw * 2;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+        const int idx = lane + kWave * s;
+        if (idx < nw) {
+            part[2 * idx] = 0.0;
+            part[2 * idx + 1] = acc[s];
+        }
+    }
+}
+
 // Band-pair resolved static evaluation: workgroup x = p * nblk + j takes the units of pair p
 // (6 Nk consecutive units) as part j of nblk; partial[q][j][pair].
 __global__ __launch_bounds__(64) void tetra_static_pairs_kernel(MeshDev M, BatchDev B, int nblk,
@@ -682,6 +792,18 @@ hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, con
     const int step = (mixed ? kFarTerms32 : kFarTerms) / kFarClasses;
     hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, step, first_chunk ? 1 : 0,
                        counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tetra_im(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
+                           int nw, double *partial, hipStream_t s)
+{
+    if (nw < 1 || nw > kMaxOmegaIm || nq < 1 || nq > kMaxQBatch || nblocks < 1) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nq), block(kWave);
+    if (nw <= 8 * kWave)
+        hipLaunchKernelGGL(tetra_im_kernel<8>, grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+    else
+        hipLaunchKernelGGL(tetra_im_kernel<16>, grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
     return hipGetLastError();
 }
 

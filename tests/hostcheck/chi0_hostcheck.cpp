@@ -113,4 +113,7 @@ void hc_near(const double *y, const double *w, double om, int fp32, double *out)
     out[0] = z.re;
     out[1] = z.im;
 }
+
+// Imaginary part alone (delta weights) on sorted nodes.
+double hc_near_im(const double *y, const double *w, double om) { return near_im(y, w, om); }
 }

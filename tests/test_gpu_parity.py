@@ -292,3 +292,30 @@ def test_static_band_pairs(nk, window):
         _say(f"q {i}: max pair error / max pair {err:.2e}")
         assert err <= TOL
         assert abs(got[i].sum() - tot[i]) <= 1e-12 * abs(tot[i])
+
+
+@pytest.mark.parametrize("n_spec", [300, 1500])
+def test_dynamic_kk_route(n_spec):
+    """The Kramers-Kronig route against the oracle's: Im (delta weights, no logarithms) against the
+    analytic oracle at every requested frequency, Re against the oracle's principal-value transform
+    of the same spectral grid; 1500 grid points make two imaginary-part launches (1024 + 776 with
+    the 300 requested frequencies)."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", nk=(8, 8, 3), nq=8, q_subset=[1, 6], nw=300)
+    lo_b, hi_b = 2, 8
+    wl.band_lo, wl.band_hi = lo_b, hi_b
+    e = wl.eps_k[lo_b:hi_b]
+    ekq = np.concatenate([q.eps_kq[lo_b:hi_b] for q in wl.qs], axis=1)
+    dmin, dmax = float(ekq.min() - e.max() - 0.05), float(ekq.max() - e.min() + 0.05)
+    plan, qs = _plan(wl)
+    om = torch.from_numpy(wl.omega).cuda()
+    _say("dynamic KK route, n_spec", n_spec)
+    got = plan.dynamic_kk(qs, om, n_spec, dmin, dmax).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0_kk(wl, i, wl.omega, n_spec, dmin, dmax)
+        exact = oracle.chi0(wl, i)
+        e_im = np.max(np.abs(got[i].imag - exact.imag)) / np.max(np.abs(exact))
+        e_re = np.max(np.abs(got[i].real - ref.real)) / np.max(np.abs(ref.real))
+        kk_vs_exact = np.max(np.abs(got[i].real - exact.real)) / np.max(np.abs(exact.real))
+        _say(f"q {i}: Im err {e_im:.2e}, Re vs oracle KK {e_re:.2e}, KK Re vs analytic {kk_vs_exact:.2e}")
+        assert e_im <= TOL and e_re <= TOL
