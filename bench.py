@@ -274,6 +274,8 @@ def main():
                     help="batch workload: divide every instance's q count by this (1 = full size)")
     ap.add_argument("--batch-workgroups", type=int, default=0, help="batch workload: K_B workgroups (0 = default)")
     ap.add_argument("--tune", action="store_true", help="batch workload: autotune the workgroups first")
+    ap.add_argument("--kk", type=int, default=0, metavar="N_SPEC",
+                    help="dynamic workloads: also time the Kramers-Kronig route with N_SPEC spectral points")
     ap.add_argument("--pairs", action="store_true",
                     help="static workloads: time the band-pair resolved call (chi0_static_pairs)")
     ap.add_argument("--n-keep", type=int, default=9, help="band window of bcc_dynamic")
@@ -425,6 +427,36 @@ def main():
             log(f"mixed {name}: {mms:.1f} ms/step, max rel err {per_q.max():.2e}")
             del mplan
         result["mixed"] = res
+
+    if args.kk:
+        # Kramers-Kronig route: Im by delta weights on a spectral grid covering every e' - e of the
+        # window, Re by the principal-value transform; error against this run's analytic FP64 result
+        ref64 = torch.view_as_complex(out).cpu().numpy()
+        e = eps[lo:hi]
+        emin, emax = float(e.min()), float(e.max())
+        ekq_min = min(float(q.eps_kq[lo:hi].min()) if q.eps_kq is not None else emin for q in qs)
+        ekq_max = max(float(q.eps_kq[lo:hi].max()) if q.eps_kq is not None else emax for q in qs)
+        spec_lo, spec_hi = ekq_min - emax - 0.01, ekq_max - emin + 0.01
+        kout = torch.empty_like(out)
+        plan.dynamic_kk(qs, om, args.kk, spec_lo, spec_hi, out=kout)
+        torch.cuda.synchronize()
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        for i in range(args.steps):
+            plan.dynamic_kk(qs, om, args.kk, spec_lo, spec_hi, out=kout)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        kms = k0.elapsed_time(k1) / args.steps
+        got = torch.view_as_complex(kout).cpu().numpy()
+        err_re = np.max(np.abs(got.real - ref64.real), axis=1) / np.max(np.abs(ref64.real), axis=1)
+        err_im = np.max(np.abs(got.imag - ref64.imag), axis=1) / np.max(np.abs(ref64), axis=1)
+        result["kk_route"] = {"value": units_per_step / (kms * 1e-3), "ms_per_step": kms,
+                              "speedup_vs_fp64": ms_step / kms, "n_spec": args.kk,
+                              "spectral_range": [spec_lo, spec_hi],
+                              "re_rel_err_vs_analytic_per_q_max": float(err_re.max()),
+                              "re_rel_err_vs_analytic_per_q_mean": float(err_re.mean()),
+                              "im_rel_err_vs_analytic_max": float(err_im.max())}
+        log(f"KK route: {kms:.1f} ms/step, Re rel err {err_re.max():.2e}, Im rel err {err_im.max():.2e}")
 
     if not args.no_cpu_baseline:
         import oracle
