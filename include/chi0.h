@@ -196,7 +196,8 @@ typedef struct chi0_batch_opts {
     int64_t workgroups;     /* tetrahedron-kernel workgroups of the whole batch, spread over the
                                items in proportion to their estimated cost (each item gets
                                1..1024 and at most one per 64 units); 0 = 32768.  The workspace
-                               is sized for this value; chi0_batch_tune only tries smaller ones. */
+                               is sized for this value and both frequency tiles;
+                               chi0_batch_tune only tries smaller counts. */
     uint64_t stage_w_bytes; /* most bytes of matrix elements W resident at once: (instance, q)
                                groups are run in stages whose W fits (a group larger than the
                                limit runs alone); 0 = one stage */
@@ -223,10 +224,11 @@ chi0_status chi0_batch_create(chi0_batch_t *out, int32_t n_inst, const chi0_inst
  * default stream).  Runs that overlap on different streams race on the workspace. */
 chi0_status chi0_batch_run(chi0_batch_t batch, void *hip_stream);
 
-/* Autotune the number of workgroups: after one warm-up run, time reps runs at the workgroup
- * count the batch was created with and at 1/2, 1/4 and 1/8 of it (not below one per item),
- * keep the fastest (synchronises hip_stream; leaves valid results in the outputs).  *chosen
- * (may be NULL) receives it. */
+/* Autotune the schedule: after one warm-up run, time reps runs for every combination of the
+ * tetrahedron-kernel workgroup count (the one the batch was created with, and 1/2, 1/4, 1/8 of
+ * it, not below one per item) and the frequency tile of an item (512 or 256 frequencies: 8 or 4
+ * frequencies per lane), keep the fastest (synchronises hip_stream; leaves valid results in the
+ * outputs).  *chosen (may be NULL) receives the workgroup count; chi0_batch_info_get the tile. */
 chi0_status chi0_batch_tune(chi0_batch_t batch, void *hip_stream, int32_t reps, int64_t *chosen);
 
 /* Schedule summary of a batch (host struct). */
@@ -236,6 +238,7 @@ typedef struct chi0_batch_info {
     int64_t workgroups[3];  /* workgroups of the matrix-element, tetrahedron and reduction
                                launches, summed over stages */
     int64_t nominal_units;  /* sum over instances of nq * 6 Nk * nbw^2 * nw */
+    int64_t omega_tile;     /* most frequencies of one item (512 unless the tuner chose 256) */
 } chi0_batch_info;
 
 chi0_status chi0_batch_info_get(chi0_batch_t batch, chi0_batch_info *info);

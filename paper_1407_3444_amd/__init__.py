@@ -63,7 +63,7 @@ class _BatchOpts(ctypes.Structure):
 
 class _BatchInfo(ctypes.Structure):
     _fields_ = [("items", ctypes.c_int64), ("stages", ctypes.c_int64), ("workgroups", ctypes.c_int64 * 3),
-                ("nominal_units", ctypes.c_int64)]
+                ("nominal_units", ctypes.c_int64), ("omega_tile", ctypes.c_int64)]
 
 
 class _Profile(ctypes.Structure):
@@ -409,4 +409,4 @@ class Chi0Batch:
         return {"items": int(inf.items), "stages": int(inf.stages),
                 "workgroups": {"contract": int(inf.workgroups[0]), "tetra": int(inf.workgroups[1]),
                                "reduce": int(inf.workgroups[2])},
-                "nominal_units": int(inf.nominal_units)}
+                "nominal_units": int(inf.nominal_units), "omega_tile": int(inf.omega_tile)}

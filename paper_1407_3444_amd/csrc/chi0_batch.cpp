@@ -112,8 +112,12 @@ chi0_status validate(int32_t n_inst, const chi0_instance *inst, const chi0_batch
     return CHI0_OK;
 }
 
-// Items, groups, stages and the workspace layout for a total of `workgroups` K_B workgroups.
-Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64_t stage_w_bytes)
+// Frequency tiles the scheduler can give an item: 4 or 8 slots of 64 per lane.
+constexpr int kChunks[2] = {kMaxOmegaPerLaunch, kMaxOmegaPerLaunch / 2};
+
+// Items, groups, stages and the workspace layout for a total of `workgroups` K_B workgroups and
+// items of at most `chunk` frequencies.
+Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64_t stage_w_bytes, int chunk)
 {
     Schedule S;
     double total_cost = 0.0;
@@ -127,12 +131,12 @@ Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64
             g.q = j;
             g.w_bytes = M.cma ? 0 : align_up(sizeof(double) * (size_t)M.nbw * M.nbw * M.nk);
             g.cost = 0.0;
-            for (int w0 = 0; w0 < inst[i].in.nw; w0 += kMaxOmegaPerLaunch) {
+            for (int w0 = 0; w0 < inst[i].in.nw; w0 += chunk) {
                 Item it;
                 it.inst = i;
                 it.q = j;
                 it.w0 = w0;
-                it.nwc = std::min(kMaxOmegaPerLaunch, inst[i].in.nw - w0);
+                it.nwc = std::min(chunk, inst[i].in.nw - w0);
                 it.rounds = rounds;
                 // carving costs about one frequency slot; every further 64 frequencies one more
                 it.cost = (double)rounds * (1.0 + (it.nwc + kWave - 1) / kWave);
@@ -260,6 +264,7 @@ struct chi0_batch_s {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int64_t workgroups = 0;
+    int chunk = kMaxOmegaPerLaunch;
     Schedule sched;
     std::vector<BatchItemDev> items;             // host images, kept alive for the uploads
     std::vector<std::vector<int32_t>> tables;
@@ -290,10 +295,10 @@ void drop_graph(chi0_batch_s *b)
     b->graph = nullptr;
 }
 
-// Schedule for `workgroups` and upload its tables (synchronous on s).
-chi0_status install(chi0_batch_s *b, int64_t workgroups, hipStream_t s)
+// Schedule for `workgroups` and frequency tile `chunk`, and upload its tables (synchronous on s).
+chi0_status install(chi0_batch_s *b, int64_t workgroups, int chunk, hipStream_t s)
 {
-    Schedule S = make_schedule(b->inst, workgroups, b->opts.stage_w_bytes);
+    Schedule S = make_schedule(b->inst, workgroups, b->opts.stage_w_bytes, chunk);
     if (S.total > b->ws_bytes) return bfail(b, CHI0_E_WORKSPACE, "workspace too small for the schedule");
     for (int k = 0; k < 3; ++k)
         if (S.blocks_total[k] > (int64_t)INT32_MAX / 256)
@@ -301,6 +306,7 @@ chi0_status install(chi0_batch_s *b, int64_t workgroups, hipStream_t s)
     drop_graph(b);
     b->sched = std::move(S);
     b->workgroups = workgroups;
+    b->chunk = chunk;
     build_tables(b->inst, b->sched, b->ws, b->items, b->tables);
     hipError_t e = hipMemcpyAsync(b->ws + b->sched.items_off, b->items.data(), sizeof(BatchItemDev) * b->items.size(),
                                   hipMemcpyHostToDevice, s);
@@ -378,7 +384,10 @@ chi0_status chi0_batch_workspace_size(int32_t n_inst, const chi0_instance *inst,
         v[i].mesh = make_mesh(inst[i].desc, inst[i].eps_k, inst[i].c_k);
     }
     const int64_t wg = (opts && opts->workgroups > 0) ? opts->workgroups : kDefaultWorkgroups;
-    *bytes = make_schedule(v, wg, opts ? opts->stage_w_bytes : 0).total;
+    // room for every frequency tile the tuner may choose
+    size_t need = 0;
+    for (int c : kChunks) need = std::max(need, make_schedule(v, wg, opts ? opts->stage_w_bytes : 0, c).total);
+    *bytes = need;
     return CHI0_OK;
 }
 
@@ -408,7 +417,7 @@ chi0_status chi0_batch_create(chi0_batch_t *out, int32_t n_inst, const chi0_inst
     b->ws_bytes = workspace_bytes;
     const int64_t wg = b->opts.workgroups > 0 ? b->opts.workgroups : kDefaultWorkgroups;
     b->opts.workgroups = wg;
-    st = install(b, wg, static_cast<hipStream_t>(stream));
+    st = install(b, wg, kMaxOmegaPerLaunch, static_cast<hipStream_t>(stream));
     if (st) {
         delete b;
         return st;
@@ -428,25 +437,29 @@ chi0_status chi0_batch_tune(chi0_batch_t b, void *stream, int32_t reps, int64_t 
     if (!b || reps < 1) return CHI0_E_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t top = b->opts.workgroups;
-    const int64_t floor_wg = (int64_t)b->sched.items.size();
-    std::vector<int64_t> cand;
-    for (int64_t g = top; cand.size() < 4; g /= 2) {
-        if (g < floor_wg) break;
-        cand.push_back(g);
+    // candidates: workgroups top, top/2, top/4, top/8 (not below one per item) x frequency tiles
+    struct Cand {
+        int64_t g;
+        int chunk;
+    };
+    std::vector<Cand> cand;
+    for (int c : kChunks) {
+        const int64_t floor_wg = (int64_t)make_schedule(b->inst, top, b->opts.stage_w_bytes, c).items.size();
+        int n = 0;
+        for (int64_t g = top; n < 4 && g >= floor_wg; g /= 2, ++n) cand.push_back({g, c});
     }
-    if (cand.empty()) cand.push_back(top);
+    if (cand.empty()) cand.push_back({top, kMaxOmegaPerLaunch});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         return bdevice(b, e, "tune events");
     }
-    int64_t best = top;
+    Cand best = cand[0];
     float best_ms = 0.0f;
     chi0_status st = CHI0_OK;
     for (size_t ci = 0; ci < cand.size(); ++ci) {
-        const int64_t g = cand[ci];
-        if ((st = install(b, g, s)) != CHI0_OK) break;
+        if ((st = install(b, cand[ci].g, cand[ci].chunk, s)) != CHI0_OK) break;
         // one untimed warm-up run before the first candidate only
         if ((ci == 0 && (e = enqueue(b, s)) != hipSuccess) || (e = hipEventRecord(e0, s)) != hipSuccess) {
             st = bdevice(b, e, "tune run");
@@ -463,17 +476,17 @@ chi0_status chi0_batch_tune(chi0_batch_t b, void *stream, int32_t reps, int64_t 
         }
         if (best_ms == 0.0f || ms < best_ms) {
             best_ms = ms;
-            best = g;
+            best = cand[ci];
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
-    if ((st = install(b, best, s)) != CHI0_OK) return st;
+    if ((st = install(b, best.g, best.chunk, s)) != CHI0_OK) return st;
     // leave the outputs valid for the chosen schedule
     if ((e = enqueue(b, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
         return bdevice(b, e, "tune final run");
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best.g;
     return CHI0_OK;
 }
 
@@ -484,6 +497,7 @@ chi0_status chi0_batch_info_get(chi0_batch_t b, chi0_batch_info *info)
     info->items = (int64_t)b->sched.items.size();
     info->stages = (int64_t)b->sched.stages.size();
     for (int k = 0; k < 3; ++k) info->workgroups[k] = b->sched.blocks_total[k];
+    info->omega_tile = b->chunk;
     for (const Inst &I : b->inst)
         info->nominal_units += (int64_t)I.in.nq * 6 * I.mesh.nk * I.mesh.nbw * I.mesh.nbw * I.in.nw;
     return CHI0_OK;

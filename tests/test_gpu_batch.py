@@ -152,6 +152,9 @@ def test_batch_tune_keeps_results(batch_setup):
     b = lib.Chi0Batch(insts, workgroups=2048, use_graph=True)
     chosen = b.tune(reps=1)
     assert chosen in (2048, 1024, 512, 256)
+    tile = b.info()["omega_tile"]
+    _say("tuned workgroups", chosen, "frequency tile", tile)
+    assert tile in (256, 512)
     tuned = [c.cpu().numpy().copy() for c in b.run()]
     torch.cuda.synchronize()
     for i, ins in enumerate(insts):
