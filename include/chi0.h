@@ -64,7 +64,9 @@ typedef enum chi0_status {
 typedef struct chi0_desc {
     int32_t nk[3];          /* mesh N1, N2, N3 (each >= 1, Nk < 2^31) */
     int32_t n_bands;        /* bands stored in the energy/eigenvector arrays (1..64) */
-    int32_t n_orb;          /* orbitals per eigenvector (1..64); ignored under cma */
+    int32_t n_orb;          /* basis functions per eigenvector: orbitals (1..64), or up to 16384
+                               plane waves (a large basis takes a four-wave MFMA contraction per
+                               k, always in FP64); ignored under cma */
     int32_t band_lo;        /* first band of the summation window (Sec. III band truncation) */
     int32_t band_hi;        /* one past the last band; <= 0 means n_bands; window <= 32 bands */
     int32_t cma;            /* 1: constant matrix elements W = 1 (Sec. III), eigenvectors unused */

@@ -173,7 +173,7 @@ chi0_status check_desc(const chi0_desc *d, const double *eps_k, const double *c_
     if (d->band_lo < 0 || d->band_lo >= hi || hi > d->n_bands) return CHI0_E_SHAPE;
     if (hi - d->band_lo > 32) return CHI0_E_SHAPE;
     if (d->cma != 0 && d->cma != 1) return CHI0_E_INVALID_ARG;
-    if (!d->cma && (d->n_orb < 1 || d->n_orb > 64)) return CHI0_E_SHAPE;
+    if (!d->cma && (d->n_orb < 1 || d->n_orb > kMaxOrb)) return CHI0_E_SHAPE;
     if (d->form != 0 && d->form != 1) return CHI0_E_INVALID_ARG;
     for (int i = 0; i < 5; ++i)
         if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;

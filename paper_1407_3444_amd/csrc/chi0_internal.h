@@ -12,6 +12,8 @@ constexpr int kWave = 64;
 constexpr int kSlots = 8;          // frequencies per lane in the dynamic kernel (8 x 64 = 512)
 constexpr int kMaxOmegaPerLaunch = kSlots * kWave;
 constexpr int kMaxOmegaIm = 16 * kWave;   // frequencies per launch of the imaginary-part kernel
+constexpr int kMaxOrbSmall = 64;          // orbital bases up to this size use the 16-k matrix-element tiles
+constexpr int kMaxOrb = 16384;            // largest basis (plane waves) of the matrix elements
 
 // Per-q data of one batch.
 struct QDev {

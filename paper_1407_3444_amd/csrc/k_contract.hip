@@ -239,6 +239,93 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
     contract_split_body<FP16>(M, B.q[blockIdx.y], (int64_t)blockIdx.x * kKPerBlock, tile);
 }
 
+// ---------------------------------------------------------------------------
+// Large bases (plane waves): the contraction length n_orb runs to thousands, so one k is a
+// genuine complex GEMM (nbw x n_orb)^H (n_orb x nbw).  One workgroup of four waves per (k, q):
+// with nbw > 16 each wave owns one 16x16 band tile over the whole reduction; with nbw <= 16 the
+// single tile's reduction is split four ways and summed through LDS.  Operands are read
+// straight from HBM (16 consecutive bands of one orbital: 256 contiguous bytes per load), the
+// waves of a workgroup sharing them through the caches.
+// ---------------------------------------------------------------------------
+constexpr int kPwWaves = 4;
+
+__global__ __launch_bounds__(256) void contract_pw_kernel(MeshDev M, BatchDev B)
+{
+    __shared__ double red[kPwWaves][8][64];
+    const QDev Q = B.q[blockIdx.y];
+    const int64_t k = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = lane & 15, kk = lane >> 4;
+    const int nb = M.nb, no = M.no;
+    const int ntile = M.nbw > 16 ? 2 : 1;
+    const int ntiles = ntile * ntile;            // 4 or 1
+    const int nsplit = kPwWaves / ntiles;        // 1 or 4 reduction slices
+    const int tile = wave % ntiles, slice = wave / ntiles;
+    const int tn = tile / ntile, tm = tile % ntile;
+    int64_t kq = k;
+    if (!Q.explicit_kq) {
+        int i2 = (int)(k % M.n3);
+        const int64_t t = k / M.n3;
+        int i1 = (int)(t % M.n2);
+        int i0 = (int)(t / M.n2);
+        i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
+        i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
+        i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
+        kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
+    }
+    const int n = tn * 16 + row, m = tm * 16 + row;
+    const bool an = n < M.nbw, bm = m < M.nbw;
+    const double *pa = M.c_k + 2 * ((k * no) * nb + M.lo + (an ? n : 0));
+    const double *pb = Q.c_kq + 2 * ((kq * no) * nb + M.lo + (bm ? m : 0));
+    // reduction slice of this wave: orbitals [o_begin, o_end) in steps of 4
+    const int steps = (no + 3) / 4;
+    const int per = (steps + nsplit - 1) / nsplit;
+    const int o_begin = slice * per * 4, o_end = min(no, (slice + 1) * per * 4);
+    dbl4 accr = {0.0, 0.0, 0.0, 0.0};
+    dbl4 acci = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int o0 = o_begin; o0 < o_end; o0 += 4) {
+        const int o = o0 + kk;
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+        if (o < o_end) {
+            const int64_t off = 2 * (int64_t)o * nb;
+            if (an) { ar = pa[off]; ai = pa[off + 1]; }
+            if (bm) { br = pb[off]; bi = pb[off + 1]; }
+        }
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, acci, 0, 0, 0);
+    }
+    if (nsplit > 1) {
+        // sum the reduction slices in a fixed order (wave 0 + 1 + 2 + 3)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            red[wave][v][lane] = accr[v];
+            red[wave][4 + v][lane] = acci[v];
+        }
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double sr = red[0][v][lane], si = red[0][4 + v][lane];
+            for (int w2 = 1; w2 < kPwWaves; ++w2) {
+                sr += red[w2][v][lane];
+                si += red[w2][4 + v][lane];
+            }
+            accr[v] = sr;
+            acci[v] = si;
+        }
+    }
+    // accumulator element v of this lane is D[kk + 4 v][row]: band n = tn*16 + kk + 4v, m = tm*16 + row
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int nn = tn * 16 + kk + 4 * v, mm = tm * 16 + row;
+        if (nn < M.nbw && mm < M.nbw)
+            Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = accr[v] * accr[v] + acci[v] * acci[v];
+    }
+}
+
 // Fused launch over the (instance, q) items of a batch: workgroup -> item from a table.
 __global__ __launch_bounds__(64) void contract_batch_kernel(const BatchItemDev *__restrict__ items,
                                                             const int32_t *__restrict__ block_item)
@@ -267,6 +354,13 @@ hipError_t launch_contract_batch(const BatchItemDev *items, const int32_t *block
 hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    if (mesh.no > kMaxOrbSmall) {
+        // large (plane-wave) bases: one four-wave workgroup per (k, q), FP64 in every precision
+        if (mesh.nbw > 32) return hipErrorInvalidValue;
+        dim3 grid((unsigned)mesh.nk, nq), block(64 * kPwWaves);
+        hipLaunchKernelGGL(contract_pw_kernel, grid, block, 0, s, mesh, batch);
+        return hipGetLastError();
+    }
     const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;
     dim3 grid((unsigned)nblk, nq), block(64);
     if (precision == 1)

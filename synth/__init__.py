@@ -32,7 +32,7 @@ __all__ = [
     "TBModel", "mesh_kfrac", "eigensystem", "sc_nn_model", "tetragonal_two_site_model",
     "bcc_spd_model", "random_model", "free_electron_eps", "Workload", "QPoint",
     "make_workload", "gamma_x_m_gamma_midpoints", "bcc_gamma_h_gamma_path", "omega_grid",
-    "band_window", "random_commensurate_shifts", "batch_workloads",
+    "band_window", "random_commensurate_shifts", "batch_workloads", "plane_wave_workload",
 ]
 
 
@@ -405,3 +405,25 @@ def batch_workloads(nq_div: int = 1, precision: int = 0) -> List[Tuple[Workload,
         wl.meta = {"model": model.name, "seed": seed, "n_orb": n_orb, "mesh": L, "nq": nq, "nw": nw}
         out.append((wl, precision))
     return out
+
+
+def plane_wave_workload(nk, n_pw: int, nb: int, nq: int, nw: int, seed: int = 7) -> Workload:
+    """Large-basis (plane-wave) stand-in: band energies of a seeded nb-orbital tetragonal model,
+    and at every k nb orthonormal eigenvector columns in an n_pw-dimensional plane-wave space
+    (QR of a seeded complex Gaussian matrix), so matrix elements are sums over n_pw coefficients
+    (Sec. III: about 4000 plane waves).  q: nq random non-zero commensurate shifts.  The
+    coefficients are not smooth in k; they exercise the contraction, not the physics."""
+    nk = tuple(int(v) for v in nk)
+    model = random_model("tetragonal", seed, nb)
+    kf = mesh_kfrac(nk)
+    eps, _ = eigensystem(model, kf)
+    rng = np.random.default_rng(seed + 1000)
+    nkt = kf.shape[0]
+    c = np.empty((nkt, n_pw, nb), dtype=np.complex128)
+    for k in range(nkt):
+        a = rng.standard_normal((n_pw, nb)) + 1j * rng.standard_normal((n_pw, nb))
+        c[k], _ = np.linalg.qr(a)
+    shifts = random_commensurate_shifts(rng, nk, nq)
+    qs = [QPoint(q_frac=np.array(sh, dtype=np.float64) / np.array(nk), shift=tuple(int(v) for v in sh)) for sh in shifts]
+    return Workload("plane_wave", nk, eps, c, qs, omega_grid(nw),
+                    meta={"model": "tetragonal", "seed": seed, "n_pw": n_pw, "nb": nb})

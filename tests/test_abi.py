@@ -194,3 +194,9 @@ def test_batch_create_checks_the_workspace_before_device_work():
     assert so.chi0_batch_create(ctypes.byref(h), 1, arr, None, None, need, None) == -5
     assert so.chi0_batch_create(ctypes.byref(h), 1, arr, None, ctypes.c_void_p(0x6000), need - 256, None) == -5
     assert not h.value
+
+
+def test_plane_wave_basis_sizes():
+    assert _plan(_desc(n_orb=4096, n_bands=8))[0] == 0
+    assert _plan(_desc(n_orb=16384, n_bands=8))[0] == 0
+    assert _plan(_desc(n_orb=16385, n_bands=8))[0] == -2

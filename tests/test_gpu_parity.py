@@ -319,3 +319,34 @@ def test_dynamic_kk_route(n_spec):
         kk_vs_exact = np.max(np.abs(got[i].real - exact.real)) / np.max(np.abs(exact.real))
         _say(f"q {i}: Im err {e_im:.2e}, Re vs oracle KK {e_re:.2e}, KK Re vs analytic {kk_vs_exact:.2e}")
         assert e_im <= TOL and e_re <= TOL
+
+
+@pytest.mark.parametrize("n_pw,nb", [(1001, 24), (998, 10)])
+def test_plane_wave_matrix_elements(n_pw, nb):
+    """Large (plane-wave) basis: the four-wave MFMA contraction per k against numpy's
+    |conj(C(k))^T C(k+q)|^2; 24 bands make four 16x16 tiles (two partial), 10 bands one tile whose
+    reduction is split four ways; basis sizes not divisible by 4."""
+    torch = _torch()
+    wl = synth.plane_wave_workload((4, 3, 3), n_pw, nb, nq=2, nw=4)
+    plan, qs = _plan(wl)
+    _say("plane-wave matrix elements", n_pw, nb)
+    n = wl.nk
+    idx = np.arange(wl.n_k).reshape(n)
+    for i, q in enumerate(wl.qs):
+        W = plan.matrix_elements(qs[i]).cpu().numpy()
+        s = q.shift
+        kq = np.roll(idx, shift=(-s[0], -s[1], -s[2]), axis=(0, 1, 2)).ravel()
+        M = np.einsum("kon,kom->nmk", wl.c_k.conj(), wl.c_k[kq])
+        assert np.max(np.abs(W - np.abs(M) ** 2)) < 1e-13
+
+
+def test_plane_wave_dynamic_chi0():
+    """chi0 with plane-wave matrix elements (300 plane waves, 6 bands) against the oracle."""
+    torch = _torch()
+    wl = synth.plane_wave_workload((4, 4, 3), 300, 6, nq=2, nw=40)
+    plan, qs = _plan(wl)
+    _say("plane-wave dynamic chi0")
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    for i in range(len(wl.qs)):
+        ref = oracle.chi0(wl, i)
+        assert _relerr(got[i], ref) <= TOL
