@@ -12,8 +12,10 @@ tetrahedron weights, ordered reduction.  Inputs are resident in HBM before the t
 region.  Prints one JSON line.
 
 --workload selects the other seeded configurations: bcc_dynamic (9-orbital bcc, 48^3,
-64 q x 512 w, --n-keep band window), tetra_static (the 10-orbital model, 256 q, static)
-and sc_cma (single-band cubic, 16^3, 8 q, static).
+64 q x 512 w, --n-keep band window), tetra_static (the 10-orbital model, 256 q, static),
+sc_cma (single-band cubic, 16^3, 8 q, static), batch (16 heterogeneous instances in one
+fused launch sequence) and pw_static (plane-wave basis: 4096 coefficients per band, 32 bands,
+12^3 mesh, 16 q, static; the matrix-element contraction against the FP64 MFMA roofline).
 """
 from __future__ import annotations
 
@@ -147,6 +149,111 @@ def bench_static(args, wl, desc):
     print(json.dumps(result), flush=True)
 
 
+def bench_pw(args):
+    """Plane-wave-basis workload: static chi0 over 16 q with matrix elements summed over 4096
+    plane-wave coefficients per band (Sec. III), so the contraction dominates the step.  The
+    roofline is that of the contraction kernel against the FP64 MFMA peak; a batched complex GEMM
+    from the vendor BLAS (torch.matmul) on the same operands of one q is timed as a yardstick."""
+    import torch
+    import paper_1407_3444_amd as lib
+    import synth
+    t0 = time.time()
+    nk, n_pw, nb, nq = (12, 12, 12), 4096, 32, 16
+    wl = synth.plane_wave_workload(nk, n_pw, nb, nq, 1, seed=11)
+    wl.static = True
+    log(f"plane-wave inputs built in {time.time() - t0:.1f}s: {wl.c_k.nbytes / 2**30:.2f} GiB of coefficients")
+    dev = torch.device("cuda:0")
+    eps, ck, qs = upload(wl, dev)
+    lo, hi = wl.window()
+    nbw = hi - lo
+    plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi)
+    ws = plan.workspace(len(qs), 1)
+    out = torch.empty(len(qs), dtype=torch.float64, device=dev)
+    for _ in range(max(1, args.warmup)):
+        plan.static(qs, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.read_profile()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.static(qs, workspace=ws, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    prof = plan.read_profile()
+    plan.profile(False)
+    log("timed", args.steps, "steps:", f"{ms:.2f} ms/step", prof)
+    units = len(qs) * 6 * wl.n_k * nbw * nbw
+    con = prof["contract"]
+    avg_ms = con["ms"] / con["launches"]
+    q_per_launch = len(qs) * args.steps / con["launches"]
+    # per (k, q): nbw^2 complex dot products of length n_pw, 8 real flops per complex term (the
+    # usual complex-GEMM count; the kernel issues three real products per term, 6 flops)
+    flops_launch = 8.0 * n_pw * nbw * nbw * wl.n_k * q_per_launch
+    mfma_flops_launch = 6.0 * n_pw * nbw * nbw * wl.n_k * q_per_launch
+    # per launch: the window's coefficients at every k once (shared by the q of the launch), at
+    # k+q once per (k, q), 16 bytes each, and the nbw^2 results per (k, q)
+    bytes_launch = (n_pw * nbw * 16.0 * (1 + q_per_launch) + nbw * nbw * 8.0 * q_per_launch) * wl.n_k
+    # the roofline counts the flops of the three-product form, the ones the matrix cores must do
+    achieved = mfma_flops_launch / (avg_ms * 1e-3) / 1e12
+    result = {"metric": METRIC, "value_form": VALUE_FORM, "value": units / (ms * 1e-3),
+              "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+              "data": "synthetic (seeded 32-orbital tight-binding energies, seeded orthonormal plane-wave "
+                      "coefficients)",
+              "config": {"workload": "plane-wave basis, 12^3 mesh, 4096 plane waves, 32 bands (all pairs), "
+                                     "16 q, static, FP64",
+                         "mesh": list(wl.nk), "n_pw": n_pw, "n_q": len(qs), "band_pairs": nbw * nbw,
+                         "units_per_step": units, "parallelism": "single GPU"},
+              "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                           "kernel": "contract_pw_kernel", "avg_launch_ms": round(avg_ms, 3),
+                           "algorithmic_bytes_per_launch": bytes_launch,
+                           "hbm_bound_ms": round(bytes_launch / 8e12 * 1e3, 3),
+                           "mfma_bound_ms": round(mfma_flops_launch / (FP64_PEAK_TFLOPS * 1e12) * 1e3, 3),
+                           "complex_gemm_equivalent_tflops": round(flops_launch / (avg_ms * 1e-3) / 1e12, 3)},
+              "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}}
+
+    # yardstick: vendor batched ZGEMM of one q (k+q coefficients gathered beforehand, untimed)
+    sh = wl.qs[0].shift
+    c5 = (ck if ck.is_complex() else torch.view_as_complex(ck)).view(*nk, n_pw, nb)[..., lo:hi]
+    a_h = c5.reshape(wl.n_k, n_pw, nbw).transpose(1, 2).conj().contiguous()
+    b = torch.roll(c5, shifts=tuple(-int(v) for v in sh), dims=(0, 1, 2)).reshape(wl.n_k, n_pw, nbw).contiguous()
+    m = torch.matmul(a_h, b)
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.steps):
+        m = torch.matmul(a_h, b)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    gms = g0.elapsed_time(g1) / args.steps
+    w_lib = (m.abs() ** 2).permute(1, 2, 0).contiguous()
+    w_ours = plan.matrix_elements(qs[0])
+    torch.cuda.synchronize()
+    diff = float((w_ours - w_lib).abs().max() / w_lib.abs().max())
+    gflops = 8.0 * n_pw * nbw * nbw * wl.n_k
+    result["vendor_zgemm_one_q"] = {"ms": gms, "tflops": gflops / (gms * 1e-3) / 1e12,
+                                    "ours_ms_per_q": avg_ms / q_per_launch, "max_rel_diff_of_W": diff}
+    log(f"vendor batched zgemm: {gms:.3f} ms/q; ours {avg_ms / q_per_launch:.3f} ms/q; W rel diff {diff:.2e}")
+    del a_h, b, m, w_lib
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.time()
+        ref = oracle.chi0(wl, 0, nthreads=threads)[0].real
+        dt = time.time() - t1
+        err = abs(float(out[0].item()) - ref) / abs(ref)
+        result["cpu_baseline"] = {"value": 6 * wl.n_k * nbw * nbw / dt, "unit": "updates/s", "cores": threads,
+                                  "kind": "oracle", "sample": f"q index 0 of {len(qs)}, full mesh, {dt:.1f} s"}
+        result["parity_sample"] = {"rel_err_vs_oracle": err, "q": 0}
+        log(f"oracle sample {dt:.1f}s, rel err {err:.2e}")
+    print(json.dumps(result), flush=True)
+
+
 def bench_batch(args):
     """The 16-instance heterogeneous batch: one fused, graph-captured launch sequence per step
     (FP64 and mixed), against the same instances as 16 sequential chi0_dynamic calls (FP64)."""
@@ -269,7 +376,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--workload", default="tetra_dynamic",
-                    choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma", "batch"])
+                    choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma", "batch", "pw_static"])
     ap.add_argument("--batch-nq-div", type=int, default=8,
                     help="batch workload: divide every instance's q count by this (1 = full size)")
     ap.add_argument("--batch-workgroups", type=int, default=0, help="batch workload: K_B workgroups (0 = default)")
@@ -302,6 +409,8 @@ def main():
     t0 = time.time()
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "pw_static":
+        return bench_pw(args)
     if args.workload == "tetra_dynamic":
         wl = synth.make_workload("tetra_dynamic", nq=64, q_subset=list(range(min(args.nq, 64))),
                                  workers=args.workers)

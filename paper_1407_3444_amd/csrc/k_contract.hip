@@ -241,27 +241,36 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
 
 // ---------------------------------------------------------------------------
 // Large bases (plane waves): the contraction length n_orb runs to thousands, so one k is a
-// genuine complex GEMM (nbw x n_orb)^H (n_orb x nbw).  One workgroup of four waves per (k, q):
-// with nbw > 16 each wave owns one 16x16 band tile over the whole reduction; with nbw <= 16 the
-// single tile's reduction is split four ways and summed through LDS.  Operands are read
-// straight from HBM (16 consecutive bands of one orbital: 256 contiguous bytes per load), the
-// waves of a workgroup sharing them through the caches.
+// genuine complex GEMM (nbw x n_orb)^H (n_orb x nbw) per q, and the q of one launch all share
+// the k operand.  A workgroup is one k and up to kPwQ q, one wave per q; each wave computes the
+// whole nbw x nbw block (NT x NT tiles of 16x16, NT = 1 or 2) over the whole reduction, so the
+// k operand is fetched from HBM once and reaches the other waves through the caches.
+//
+// The complex product takes three real MFMAs instead of four (Gauss): with a = C(k) and
+// b = C(k+q) per orbital,
+//     P = sum (ar + ai)(br + bi),  R = sum ar bi,  S = sum ai br,
+//     Re M = sum (ar br + ai bi) = P - R - S,   Im M = sum (ar bi - ai br) = R - S,
+// and |M|^2 is formed from the three accumulators at the end.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs.  The launch is 1-D and block b runs
+// (k, qgroup) with xcd = b % 8: the q-groups of one k sit on consecutive slots of the same XCD,
+// so their k operand is shared in that XCD's L2.
 // ---------------------------------------------------------------------------
-constexpr int kPwWaves = 4;
+constexpr int kPwQ = 8;      // q (waves) per workgroup
+constexpr int kXcd = 8;
+constexpr int kPwDepth = 4;  // steps of operands in flight per wave
 
-__global__ __launch_bounds__(256) void contract_pw_kernel(MeshDev M, BatchDev B)
+template <int NT>
+__global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups)
 {
-    __shared__ double red[kPwWaves][8][64];
-    const QDev Q = B.q[blockIdx.y];
-    const int64_t k = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = lane & 15, kk = lane >> 4;
-    const int nb = M.nb, no = M.no;
-    const int ntile = M.nbw > 16 ? 2 : 1;
-    const int ntiles = ntile * ntile;            // 4 or 1
-    const int nsplit = kPwWaves / ntiles;        // 1 or 4 reduction slices
-    const int tile = wave % ntiles, slice = wave / ntiles;
-    const int tn = tile / ntile, tm = tile % ntile;
+    const int64_t b = blockIdx.x;
+    const int xcd = (int)(b % kXcd);
+    const int64_t slot = b / kXcd;
+    const int64_t k = (slot / n_qgroups) * kXcd + xcd;
+    const int qi = (int)(slot % n_qgroups) * kPwQ + wave;
+    if (k >= M.nk || qi >= nq) return;      // no barriers below: a wave may leave on its own
+    const QDev Q = B.q[qi];
     int64_t kq = k;
     if (!Q.explicit_kq) {
         int i2 = (int)(k % M.n3);
@@ -273,57 +282,90 @@ __global__ __launch_bounds__(256) void contract_pw_kernel(MeshDev M, BatchDev B)
         i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
         kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
     }
-    const int n = tn * 16 + row, m = tm * 16 + row;
-    const bool an = n < M.nbw, bm = m < M.nbw;
-    const double *pa = M.c_k + 2 * ((k * no) * nb + M.lo + (an ? n : 0));
-    const double *pb = Q.c_kq + 2 * ((kq * no) * nb + M.lo + (bm ? m : 0));
-    // reduction slice of this wave: orbitals [o_begin, o_end) in steps of 4
-    const int steps = (no + 3) / 4;
-    const int per = (steps + nsplit - 1) / nsplit;
-    const int o_begin = slice * per * 4, o_end = min(no, (slice + 1) * per * 4);
-    dbl4 accr = {0.0, 0.0, 0.0, 0.0};
-    dbl4 acci = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int o0 = o_begin; o0 < o_end; o0 += 4) {
-        const int o = o0 + kk;
-        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-        if (o < o_end) {
-            const int64_t off = 2 * (int64_t)o * nb;
-            if (an) { ar = pa[off]; ai = pa[off + 1]; }
-            if (bm) { br = pb[off]; bi = pb[off + 1]; }
-        }
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, acci, 0, 0, 0);
+    const int row = lane & 15, kk = lane >> 4;
+    const int nb = M.nb, no = M.no;
+    // operand rows of this lane: band t*16 + row of C(k) (A) and of C(k+q) (B), orbital o0 + kk
+    const double *pa[NT];
+    const double *pb[NT];
+    bool ok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = t * 16 + row;
+        ok[t] = n < M.nbw;
+        pa[t] = M.c_k + 2 * ((k * no) * nb + M.lo + (ok[t] ? n : 0));
+        pb[t] = Q.c_kq + 2 * ((kq * no) * nb + M.lo + (ok[t] ? n : 0));
     }
-    if (nsplit > 1) {
-        // sum the reduction slices in a fixed order (wave 0 + 1 + 2 + 3)
+    // one accumulator set per tile pair; with a single tile, two sets over alternating steps
+    constexpr int NS = NT == 1 ? 2 : 1;
+    dbl4 accP[NS][NT][NT], accR[NS][NT][NT], accS[NS][NT][NT];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            red[wave][v][lane] = accr[v];
-            red[wave][4 + v][lane] = acci[v];
-        }
-        __syncthreads();
-        if (wave != 0) return;
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double sr = red[0][v][lane], si = red[0][4 + v][lane];
-            for (int w2 = 1; w2 < kPwWaves; ++w2) {
-                sr += red[w2][v][lane];
-                si += red[w2][4 + v][lane];
+        for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+            for (int tm = 0; tm < NT; ++tm) {
+                accP[s][tn][tm] = dbl4{0.0, 0.0, 0.0, 0.0};
+                accR[s][tn][tm] = dbl4{0.0, 0.0, 0.0, 0.0};
+                accS[s][tn][tm] = dbl4{0.0, 0.0, 0.0, 0.0};
             }
-            accr[v] = sr;
-            acci[v] = si;
+    // operands of kPwDepth steps of 4 orbitals in flight: the slot of a step is refilled with
+    // the step kPwDepth later as soon as its MFMAs have been issued
+    double ar[kPwDepth][NT], ai[kPwDepth][NT], br[kPwDepth][NT], bi[kPwDepth][NT];
+    // Loads are unconditional (past the last orbital the address is clamped to it and the value
+    // replaced by zero), so no branch separates a load from its use and the wait counters can let
+    // the later steps' loads stay in flight.
+    auto fetch = [&](int d, int o) {
+        const int64_t off = 2 * (int64_t)min(o, no - 1) * nb;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bool use = o < no && ok[t];
+            const double2 a = *reinterpret_cast<const double2 *>(pa[t] + off);
+            const double2 b = *reinterpret_cast<const double2 *>(pb[t] + off);
+            ar[d][t] = use ? a.x : 0.0;
+            ai[d][t] = use ? a.y : 0.0;
+            br[d][t] = use ? b.x : 0.0;
+            bi[d][t] = use ? b.y : 0.0;
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < kPwDepth; ++d) fetch(d, 4 * d + kk);
+    for (int o0 = 0; o0 < no; o0 += 4 * kPwDepth) {
+#pragma unroll
+        for (int d = 0; d < kPwDepth; ++d) {
+            const int s = d % NS;
+#pragma unroll
+            for (int tn = 0; tn < NT; ++tn) {
+                const double as = ar[d][tn] + ai[d][tn];
+#pragma unroll
+                for (int tm = 0; tm < NT; ++tm) {
+                    const double bs = br[d][tm] + bi[d][tm];
+                    accP[s][tn][tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bs, accP[s][tn][tm], 0, 0, 0);
+                    accR[s][tn][tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[d][tn], bi[d][tm], accR[s][tn][tm], 0, 0, 0);
+                    accS[s][tn][tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[d][tn], br[d][tm], accS[s][tn][tm], 0, 0, 0);
+                }
+            }
+            fetch(d, o0 + 4 * (d + kPwDepth) + kk);
         }
     }
     // accumulator element v of this lane is D[kk + 4 v][row]: band n = tn*16 + kk + 4v, m = tm*16 + row
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int nn = tn * 16 + kk + 4 * v, mm = tm * 16 + row;
-        if (nn < M.nbw && mm < M.nbw)
-            Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = accr[v] * accr[v] + acci[v] * acci[v];
-    }
+    for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < NT; ++tm)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double P = accP[0][tn][tm][v], R = accR[0][tn][tm][v], S = accS[0][tn][tm][v];
+#pragma unroll
+                for (int s = 1; s < NS; ++s) {
+                    P += accP[s][tn][tm][v];
+                    R += accR[s][tn][tm][v];
+                    S += accS[s][tn][tm][v];
+                }
+                const double re = P - R - S, im = R - S;
+                const int nn = tn * 16 + kk + 4 * v, mm = tm * 16 + row;
+                if (nn < M.nbw && mm < M.nbw)
+                    Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = re * re + im * im;
+            }
 }
 
 // Fused launch over the (instance, q) items of a batch: workgroup -> item from a table.
@@ -355,10 +397,18 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     if (mesh.no > kMaxOrbSmall) {
-        // large (plane-wave) bases: one four-wave workgroup per (k, q), FP64 in every precision
+        // large (plane-wave) bases: one workgroup per (k, group of kPwQ q), FP64 in every precision
         if (mesh.nbw > 32) return hipErrorInvalidValue;
-        dim3 grid((unsigned)mesh.nk, nq), block(64 * kPwWaves);
-        hipLaunchKernelGGL(contract_pw_kernel, grid, block, 0, s, mesh, batch);
+        const int ng = (nq + kPwQ - 1) / kPwQ;
+        const int64_t k_per_xcd = (mesh.nk + kXcd - 1) / kXcd;
+        const int64_t nblk = k_per_xcd * kXcd * ng;
+        if (nblk >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+        if (mesh.nbw > 16)
+            hipLaunchKernelGGL(contract_pw_kernel<2>, dim3((unsigned)nblk), dim3(64 * kPwQ), 0, s, mesh, batch,
+                               nq, ng);
+        else
+            hipLaunchKernelGGL(contract_pw_kernel<1>, dim3((unsigned)nblk), dim3(64 * kPwQ), 0, s, mesh, batch,
+                               nq, ng);
         return hipGetLastError();
     }
     const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;

@@ -410,7 +410,7 @@ def batch_workloads(nq_div: int = 1, precision: int = 0) -> List[Tuple[Workload,
 def plane_wave_workload(nk, n_pw: int, nb: int, nq: int, nw: int, seed: int = 7) -> Workload:
     """Large-basis (plane-wave) stand-in: band energies of a seeded nb-orbital tetragonal model,
     and at every k nb orthonormal eigenvector columns in an n_pw-dimensional plane-wave space
-    (QR of a seeded complex Gaussian matrix), so matrix elements are sums over n_pw coefficients
+    (Cholesky QR of a seeded complex Gaussian matrix), so matrix elements are sums over n_pw coefficients
     (Sec. III: about 4000 plane waves).  q: nq random non-zero commensurate shifts.  The
     coefficients are not smooth in k; they exercise the contraction, not the physics."""
     nk = tuple(int(v) for v in nk)
@@ -420,9 +420,13 @@ def plane_wave_workload(nk, n_pw: int, nb: int, nq: int, nw: int, seed: int = 7)
     rng = np.random.default_rng(seed + 1000)
     nkt = kf.shape[0]
     c = np.empty((nkt, n_pw, nb), dtype=np.complex128)
-    for k in range(nkt):
-        a = rng.standard_normal((n_pw, nb)) + 1j * rng.standard_normal((n_pw, nb))
-        c[k], _ = np.linalg.qr(a)
+    for k0 in range(0, nkt, 64):
+        k1 = min(nkt, k0 + 64)
+        a = rng.standard_normal((k1 - k0, n_pw, nb)) + 1j * rng.standard_normal((k1 - k0, n_pw, nb))
+        # orthonormal columns by Cholesky QR (a Gaussian block is well conditioned)
+        g = np.matmul(a.conj().transpose(0, 2, 1), a)
+        r_inv = np.linalg.inv(np.linalg.cholesky(g).conj().transpose(0, 2, 1))
+        c[k0:k1] = np.matmul(a, r_inv)
     shifts = random_commensurate_shifts(rng, nk, nq)
     qs = [QPoint(q_frac=np.array(sh, dtype=np.float64) / np.array(nk), shift=tuple(int(v) for v in sh)) for sh in shifts]
     return Workload("plane_wave", nk, eps, c, qs, omega_grid(nw),

@@ -321,15 +321,19 @@ def test_dynamic_kk_route(n_spec):
         assert e_im <= TOL and e_re <= TOL
 
 
-@pytest.mark.parametrize("n_pw,nb", [(1001, 24), (998, 10)])
-def test_plane_wave_matrix_elements(n_pw, nb):
-    """Large (plane-wave) basis: the four-wave MFMA contraction per k against numpy's
-    |conj(C(k))^T C(k+q)|^2; 24 bands make four 16x16 tiles (two partial), 10 bands one tile whose
-    reduction is split four ways; basis sizes not divisible by 4."""
+@pytest.mark.parametrize("n_pw,nb,nq", [(1001, 24, 2), (998, 10, 11)])
+def test_plane_wave_matrix_elements(n_pw, nb, nq):
+    """Large (plane-wave) basis: the MFMA contraction (one wave per q, three real products per
+    complex product) against numpy's |conj(C(k))^T C(k+q)|^2; 24 bands make 2x2 16x16 tiles (the
+    last ones partial), 10 bands one partial tile; basis sizes not divisible by 4 or 8; 11 q fill
+    one workgroup of q and part of a second, on a mesh (36 points) that is not a multiple of the
+    8 XCDs.  Static chi0 of all q in one call (one launch of the contraction) must equal the
+    calls with one q each (to rounding of the reduction partition) and the oracle within the FP64
+    bar."""
     torch = _torch()
-    wl = synth.plane_wave_workload((4, 3, 3), n_pw, nb, nq=2, nw=4)
+    wl = synth.plane_wave_workload((4, 3, 3), n_pw, nb, nq=nq, nw=4)
     plan, qs = _plan(wl)
-    _say("plane-wave matrix elements", n_pw, nb)
+    _say("plane-wave matrix elements", n_pw, nb, nq)
     n = wl.nk
     idx = np.arange(wl.n_k).reshape(n)
     for i, q in enumerate(wl.qs):
@@ -338,6 +342,13 @@ def test_plane_wave_matrix_elements(n_pw, nb):
         kq = np.roll(idx, shift=(-s[0], -s[1], -s[2]), axis=(0, 1, 2)).ravel()
         M = np.einsum("kon,kom->nmk", wl.c_k.conj(), wl.c_k[kq])
         assert np.max(np.abs(W - np.abs(M) ** 2)) < 1e-13
+    # all q in one launch (q-groups of one workgroup) against one q per call, and the oracle
+    together = plan.static(qs).cpu().numpy()
+    for i in range(nq):
+        alone = plan.static([qs[i]]).cpu().numpy()
+        assert abs(alone[0] - together[i]) <= 1e-13 * abs(together[i]), i
+        ref = oracle.chi0(wl, i, omega=np.zeros(1))[0].real
+        assert abs(together[i] - ref) <= TOL * abs(ref), (i, together[i], ref)
 
 
 def test_plane_wave_dynamic_chi0():
