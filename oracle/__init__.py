@@ -51,6 +51,9 @@ def _load():
         lib.chi0_oracle_dd5.restype = None
         lib.chi0_oracle_carve.argtypes = [dp, dp, i, dp, dp]
         lib.chi0_oracle_carve.restype = i
+        lib.chi0_oracle_list.argtypes = [i, i, i, dp, dp, dp, dp, ll, ctypes.POINTER(ctypes.c_int), d, d, d, i, i,
+                                         i, i, i, dp, i, dp]
+        lib.chi0_oracle_list.restype = i
         lib.chi0_oracle_tet_corners.argtypes = [i, i, i, ll, i, ctypes.POINTER(ctypes.c_longlong)]
         lib.chi0_oracle_tet_corners.restype = None
         _lib = lib
@@ -95,6 +98,90 @@ def chi0_raw(nk, eps_k, c_k, omega, *, eps_kq=None, c_kq=None, shift=(0, 0, 0), 
     if rc != 0:
         raise ValueError("chi0_oracle failed with code %d" % rc)
     return out[:, 0] + 1j * out[:, 1]
+
+
+def chi0_list(eps_k, c_k, eps_kq, c_kq, tets, volume: float, omega, *, mu=0.0, spin_factor=2.0, band_lo=0,
+              band_hi=-1, cma=False, form=0, nthreads: int = 0) -> np.ndarray:
+    """chi0 at one q over an explicit list of tetrahedra (corner indices tets [n_tet][4] into the
+    k-points of eps_k [nb][n_kp]; eps_kq/c_kq hold the data at the same points shifted by q; each
+    tetrahedron is the fraction `volume` of the zone): complex array [nw]."""
+    lib = _load()
+    eps_k = _f64(eps_k)
+    nb, n_kp = eps_k.shape
+    no = 1 if c_k is None else c_k.shape[1]
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    omega = _f64(np.atleast_1d(omega))
+    out = np.zeros((omega.size, 2))
+    ck, ckq = (None, None) if cma else (_c128_as_f64(c_k), _c128_as_f64(c_kq))
+    rc = lib.chi0_oracle_list(int(n_kp), nb, no, _ptr(eps_k), _ptr(ck), _ptr(_f64(eps_kq)), _ptr(ckq),
+                              tets.shape[0], tets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(volume),
+                              float(mu), float(spin_factor), int(band_lo), int(band_hi), int(bool(cma)), int(form),
+                              omega.size, _ptr(omega), int(nthreads), _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle_list failed with code %d" % rc)
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def cubic_point_group() -> np.ndarray:
+    """The 48 operations of O_h as integer matrices acting on fractional coordinates of a simple
+    cubic reciprocal lattice (signed permutation matrices), identity first."""
+    import itertools
+    ops = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            g = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                g[r, perm[r]] = signs[r]
+            ops.append(g)
+    ops.sort(key=lambda g: (not np.array_equal(g, np.eye(3, dtype=np.int64)),))
+    return np.array(ops)
+
+
+def iw_cubic(n: int):
+    """Irreducible wedge of a Gamma-centred n x n x n simple-cubic mesh (n even) under O_h,
+    decomposed into tetrahedra (Sec. II, Fig. 1(a)).
+
+    The wedge is 0 <= z <= y <= x <= 1/2 (fractional).  A cube of the mesh with integer corner
+    (i, j, l), i >= j >= l, splits into six tetrahedra by the order in which the three axes are
+    stepped from its corner to the opposite one; a tetrahedron lies in the wedge unless the cube
+    sits on the plane x = y (i == j) and the tetrahedron steps y before x, or on y = z (j == l)
+    and it steps z before y.  Returns (kfrac [n_kp][3], tets [n_tet][4] int32, volume of one
+    tetrahedron as a fraction of the zone)."""
+    import itertools
+    if n < 2 or n % 2:
+        raise ValueError("n must be even and >= 2")
+    m = n // 2
+    pts = [(i, j, l) for i in range(m + 1) for j in range(i + 1) for l in range(j + 1)]
+    where = {p: t for t, p in enumerate(pts)}
+    tets = []
+    for i in range(m):
+        for j in range(i + 1):
+            for l in range(j + 1):
+                for order in itertools.permutations(range(3)):
+                    rank = {ax: r for r, ax in enumerate(order)}
+                    if i == j and rank[0] > rank[1]:
+                        continue
+                    if j == l and rank[1] > rank[2]:
+                        continue
+                    c = [i, j, l]
+                    corners = [where[tuple(c)]]
+                    for ax in order:
+                        c[ax] += 1
+                        corners.append(where[tuple(c)])
+                    tets.append(corners)
+    kfrac = np.array(pts, dtype=np.float64) / n
+    return kfrac, np.array(tets, dtype=np.int32), 1.0 / (6.0 * n ** 3)
+
+
+def chi0_iw(eps_k, c_k, entries, tets, volume: float, omega, **kw) -> np.ndarray:
+    """The point-group loop of Sec. II: the second carving is repeated for every point-group
+    element g, each with the k+q data of the wedge's points taken at k + g^-1 q; entries is the
+    list of (eps_kq, c_kq) per g and the result the sum of the per-g wedge integrals."""
+    total = None
+    for eps_kq, c_kq in entries:
+        part = chi0_list(eps_k, c_k, eps_kq, c_kq, tets, volume, omega, **kw)
+        total = part if total is None else total + part
+    return total
 
 
 def chi0(wl, q_index: int, omega=None, cells=None, nthreads: int = 0, form: Optional[int] = None) -> np.ndarray:

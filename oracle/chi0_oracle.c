@@ -393,14 +393,12 @@ static void add_piece(const btet *S, const double Dc[4], const double Wc[4], dou
     }
 }
 
-/* Contributions of one mesh tetrahedron, all band pairs.  Pair (n, m) adds into
- * acc + (n * nbw + m) * pair_stride (pair_stride = 0: every pair into acc). */
-static void tet_contribution(const problem *P, long long cell, int t, int nw, const double *omega, cplx *acc,
-                             long long pair_stride)
+/* Contributions of one tetrahedron whose corners are the k-points idx[4] (k+q data at
+ * idq[4]), all band pairs.  Pair (n, m) adds into acc + (n * nbw + m) * pair_stride
+ * (pair_stride = 0: every pair into acc). */
+static void tet_contribution_at(const problem *P, const long long idx[4], const long long idq[4], int nw,
+                                const double *omega, cplx *acc, long long pair_stride)
 {
-    long long idx[4], idq[4];
-    tet_corners(P->n, cell, t, idx);
-    for (int c = 0; c < 4; ++c) idq[c] = kq_index(P, idx[c]);
     const double *ekq = P->eps_kq ? P->eps_kq : P->eps_k;
     for (int n = 0; n < P->nbw; ++n)
         for (int m = 0; m < P->nbw; ++m) {
@@ -422,6 +420,16 @@ static void tet_contribution(const problem *P, long long cell, int t, int nw, co
                 for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, pacc);
             }
         }
+}
+
+/* Contributions of one mesh tetrahedron (cell, Kuhn tetrahedron t), all band pairs. */
+static void tet_contribution(const problem *P, long long cell, int t, int nw, const double *omega, cplx *acc,
+                             long long pair_stride)
+{
+    long long idx[4], idq[4];
+    tet_corners(P->n, cell, t, idx);
+    for (int c = 0; c < 4; ++c) idq[c] = kq_index(P, idx[c]);
+    tet_contribution_at(P, idx, idq, nw, omega, acc, pair_stride);
 }
 
 static int setup(problem *P, int n1, int n2, int n3, int nb, int no,
@@ -488,6 +496,63 @@ int chi0_oracle(int n1, int n2, int n3, int nb, int no,
             for (int t = 0; t < 6; ++t) tet_contribution(&P, cell, t, nw, omega, my, 0);
     }
     double pref = spin_factor / (6.0 * (double)P.nk);
+    for (int iw = 0; iw < nw; ++iw) {
+        cplx s = 0.0;
+        for (int t = 0; t < nt; ++t) s += acc[(size_t)t * nw + iw];   /* fixed order */
+        out[2 * iw] = pref * creal(s);
+        out[2 * iw + 1] = pref * cimag(s);
+    }
+    free(acc);
+    free(P.W);
+    return 0;
+}
+
+/*
+ * chi0 at one q summed over an explicit list of tetrahedra instead of the mesh's Kuhn
+ * tetrahedra: the irreducible wedge of Sec. II decomposed into tetrahedra, or any other set.
+ * tets[n_tet][4] are corner indices into n_kp k-points; eps_k [nb][n_kp] and c_k
+ * [n_kp][no][nb] hold the data at those points, eps_kq [nb][n_kp] and c_kq [n_kp][no][nb]
+ * (c_kq may be NULL under CMA) the data at the same points shifted by q.  Every tetrahedron
+ * is the fraction `volume` of the zone.  out: [nw][2] = (Re, Im).  Returns 0 on success.
+ */
+int chi0_oracle_list(int n_kp, int nb, int no,
+                     const double *eps_k, const double *c_k,
+                     const double *eps_kq, const double *c_kq,
+                     long long n_tet, const int *tets, double volume,
+                     double mu, double spin_factor, int band_lo, int band_hi,
+                     int cma, int form, int nw, const double *omega, int nthreads, double *out)
+{
+    if (!eps_kq || !tets || n_tet < 0 || !(volume > 0.0)) return -1;
+    for (long long t = 0; t < 4 * n_tet; ++t)
+        if (tets[t] < 0 || tets[t] >= n_kp) return -2;
+    problem P;
+    int rc = setup(&P, n_kp, 1, 1, nb, no, eps_k, c_k, eps_kq, cma ? NULL : c_kq, 0, 0, 0, mu,
+                   band_lo, band_hi, cma, form);
+    if (rc) return rc;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    cplx *acc = (cplx *)calloc((size_t)nt * nw, sizeof(cplx));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        cplx *my = acc + (size_t)tid * nw;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (long long t = 0; t < n_tet; ++t) {
+            long long idx[4];
+            for (int c = 0; c < 4; ++c) idx[c] = tets[4 * t + c];
+            tet_contribution_at(&P, idx, idx, nw, omega, my, 0);
+        }
+    }
+    double pref = spin_factor * volume;
     for (int iw = 0; iw < nw; ++iw) {
         cplx s = 0.0;
         for (int t = 0; t < nt; ++t) s += acc[(size_t)t * nw + iw];   /* fixed order */

@@ -33,6 +33,7 @@ __all__ = [
     "bcc_spd_model", "random_model", "free_electron_eps", "Workload", "QPoint",
     "make_workload", "gamma_x_m_gamma_midpoints", "bcc_gamma_h_gamma_path", "omega_grid",
     "band_window", "random_commensurate_shifts", "batch_workloads", "plane_wave_workload",
+    "cubic_s_model", "free_electron_eps_at",
 ]
 
 
@@ -86,6 +87,27 @@ def sc_nn_model(t: float = 1.0) -> TBModel:
     for R in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
         _add_pair(hop, R, np.array([[-t]]))
     return TBModel("sc_nn", 1, hop, {"t": t})
+
+
+def cubic_s_model(seed: int, n_orb: int = 3, sigma: float = 0.5) -> TBModel:
+    """Simple-cubic model with n_orb s-like orbitals per site: a seeded symmetric onsite matrix
+    and one symmetric hopping matrix per shell (the 6 nearest and the 12 next-nearest neighbours),
+    the same for every bond of the shell, so H(g k) = H(k) for every cubic point-group operation g
+    and the bands and |<n k|m k+q>|^2 are invariant under the whole group."""
+    rng = np.random.default_rng(seed)
+    hop: dict = {}
+
+    def sym(scale):
+        a = rng.normal(0.0, scale, (n_orb, n_orb))
+        return 0.5 * (a + a.T)
+
+    _add_pair(hop, (0, 0, 0), np.diag(rng.uniform(-1.0, 1.0, n_orb)) + sym(0.3 * sigma))
+    t1, t2 = sym(sigma), sym(0.5 * sigma)
+    for R in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+        _add_pair(hop, R, t1)
+    for R in [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)]:
+        _add_pair(hop, R, t2)
+    return TBModel("cubic_s", n_orb, hop, {"seed": seed, "sigma": sigma})
 
 
 def tetragonal_two_site_model(seed: int, sigma: float = 0.3) -> TBModel:
@@ -174,6 +196,12 @@ def free_electron_eps(nk: Sequence[int], q_cart=(0.0, 0.0, 0.0)) -> np.ndarray:
     n = np.asarray(nk)
     frac = mesh_kfrac(nk)
     k = 2.0 * np.pi * frac - np.pi + np.asarray(q_cart, dtype=np.float64)[None, :]
+    return (0.5 * np.sum(k * k, axis=1))[None, :].copy()
+
+
+def free_electron_eps_at(kfrac: np.ndarray, q_cart=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """eps = |k + q|^2 / 2 at k = 2 pi kfrac (Gamma-centred fractional points, a = 1), shape (1, n)."""
+    k = 2.0 * np.pi * np.asarray(kfrac, dtype=np.float64) + np.asarray(q_cart, dtype=np.float64)[None, :]
     return (0.5 * np.sum(k * k, axis=1))[None, :].copy()
 
 
