@@ -65,8 +65,9 @@ typedef struct chi0_desc {
     int32_t nk[3];          /* mesh N1, N2, N3 (each >= 1, Nk < 2^31) */
     int32_t n_bands;        /* bands stored in the energy/eigenvector arrays (1..64) */
     int32_t n_orb;          /* basis functions per eigenvector: orbitals (1..64), or up to 16384
-                               plane waves (a large basis takes a four-wave MFMA contraction per
-                               k, always in FP64); ignored under cma */
+                               plane waves (a basis above 64 takes the plane-wave MFMA contraction,
+                               one wave per q sharing the k operand, always in FP64); ignored
+                               under cma */
     int32_t band_lo;        /* first band of the summation window (Sec. III band truncation) */
     int32_t band_hi;        /* one past the last band; <= 0 means n_bands; window <= 32 bands */
     int32_t cma;            /* 1: constant matrix elements W = 1 (Sec. III), eigenvectors unused */
@@ -147,6 +148,61 @@ chi0_status chi0_dynamic_kk(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int3
  * n, m relative to band_lo, nbw = band_hi - band_lo.  W: device float64 [nbw][nbw][Nk].
  * CHI0_E_UNSUPPORTED under cma. */
 chi0_status chi0_matrix_elements(chi0_plan_t plan, const chi0_q *q, double *W);
+
+/* ------------------------------------------------------------------------------------------
+ * Irreducible wedge and point-group loop (Sec. II).  The paper integrates over the irreducible
+ * wedge (IW) of the zone decomposed into tetrahedra and repeats the second carving for every
+ * point-group element g of the crystal.  For bands and matrix elements invariant under the group,
+ * the zone integral at q equals the sum over g of the wedge integral with the k+q data taken at
+ * k + g^-1 q.  A list plan integrates over an explicit tetrahedron list (the wedge); the group
+ * calls sum the results of groups of q-entries (one entry per g) inside the reduction kernel.
+ * ------------------------------------------------------------------------------------------ */
+
+/* An explicit set of tetrahedra replacing the mesh's Kuhn tetrahedra. */
+typedef struct chi0_tetra_list {
+    int64_t n_kp;           /* k-points of the band arrays: eps_k [n_bands][n_kp] and c_k
+                               [n_kp][n_orb][n_bands]; 1 <= n_kp < 2^31 */
+    int64_t n_tet;          /* tetrahedra, 1 <= n_tet < 2^31 */
+    const int32_t *tets;    /* device int32 [n_tet][4], 16-byte aligned: the corner k-point
+                               indices of every tetrahedron; chi0_plan_list copies them to the
+                               host once and rejects any index outside [0, n_kp) (CHI0_E_SHAPE) */
+    double volume;          /* fraction of the zone one tetrahedron covers (> 0); the result is
+                               spin_factor * volume * (sum over tetrahedra), so 1/(6 N1 N2 N3)
+                               for tetrahedra of an N1 x N2 x N3 mesh */
+} chi0_tetra_list;
+
+/* Create a plan over a tetrahedron list.  desc as for chi0_plan except that desc->nk is not used;
+ * eps_k: device [n_bands][n_kp]; c_k: device [n_kp][n_orb][n_bands] complex128 (NULL under cma).
+ * Every q given to this plan must be explicit (explicit_kq = 1, eps_kq [n_bands][n_kp] and c_kq
+ * [n_kp][n_orb][n_bands] at the list's k-points shifted by q); a mesh shift is rejected with
+ * CHI0_E_INVALID_ARG.  All calls of a mesh plan are available except the batched form.  The
+ * plan borrows list->tets as it borrows eps_k and c_k.  Synchronises the stream once (the index
+ * check). */
+chi0_status chi0_plan_list(chi0_plan_t *out, const chi0_desc *desc, const chi0_tetra_list *list,
+                           const double *eps_k, const double *c_k, void *hip_stream);
+
+/* Group sums (the point-group loop): qs holds nq * n_group entries, group i being entries
+ * i * n_group .. i * n_group + n_group - 1 (one per point-group element, each with its k+q data);
+ * chi receives, per group, the sum of the group's chi0 values: device float64 [nq] (static) or
+ * [nq][nw][2] (dynamic).  Each group is summed in entry order inside the reduction kernel (groups
+ * of more than 16 entries over several launches, each added to the previous total).  Workspace:
+ * chi0_workspace_size(plan, nq * n_group, nw). */
+chi0_status chi0_static_group(chi0_plan_t plan, int32_t nq, int32_t n_group, const chi0_q *qs, void *workspace,
+                              size_t workspace_bytes, double *chi);
+chi0_status chi0_dynamic_group(chi0_plan_t plan, int32_t nq, int32_t n_group, const chi0_q *qs, int32_t nw,
+                               const double *omega, void *workspace, size_t workspace_bytes, double *chi);
+
+/* The irreducible wedge 0 <= z <= y <= x <= 1/2 (fractional coordinates) of a Gamma-centred
+ * n x n x n simple-cubic mesh (n even, 2..1024) under the 48-element cubic group O_h, as
+ * tetrahedra: every mesh cube i >= j >= l >= 0 in the wedge split into the six tetrahedra of the
+ * three axis orders from its corner (0,0,0) to (1,1,1), keeping those inside the wedge (Fig. 1(a)).
+ * Host memory.  *n_kp receives the (n/2+1)(n/2+2)(n/2+3)/6 wedge points, *n_tet the (n/2)^3
+ * tetrahedra, *volume 1/(6 n^3); when non-NULL, kfrac [n_kp][3] receives the points, tets
+ * [n_tet][4] the corner indices and ops [48][3][3] the group's integer matrices acting on
+ * fractional coordinates (signed permutations, identity first).  Call first with NULL arrays for
+ * the sizes. */
+chi0_status chi0_iw_cubic(int32_t n, int64_t *n_kp, int64_t *n_tet, double *volume, double *kfrac,
+                          int32_t *tets, int32_t *ops);
 
 /* Kernel timing of the plan's launches, measured with HIP events on the plan's stream
  * while profiling is enabled.  Index 0: matrix-element kernel, 1: tetrahedron kernel,

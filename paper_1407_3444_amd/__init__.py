@@ -16,13 +16,14 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
-__all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library", "LIB_PATH",
+__all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library", "LIB_PATH", "iw_cubic",
            "EXPORTED_SYMBOLS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
 EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
-                    "chi0_kk_workspace_size", "chi0_dynamic_kk",
+                    "chi0_kk_workspace_size", "chi0_dynamic_kk", "chi0_plan_list", "chi0_static_group",
+                    "chi0_dynamic_group", "chi0_iw_cubic",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                     "chi0_destroy", "chi0_status_string", "chi0_last_error", "chi0_batch_workspace_size",
                     "chi0_batch_create", "chi0_batch_run", "chi0_batch_tune", "chi0_batch_info_get",
@@ -66,6 +67,11 @@ class _BatchInfo(ctypes.Structure):
                 ("nominal_units", ctypes.c_int64), ("omega_tile", ctypes.c_int64)]
 
 
+class _TetraList(ctypes.Structure):
+    _fields_ = [("n_kp", ctypes.c_int64), ("n_tet", ctypes.c_int64), ("tets", ctypes.c_void_p),
+                ("volume", ctypes.c_double)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_int64 * 3)]
 
@@ -94,6 +100,11 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_profile_enable.argtypes = [vp, i32]
     lib.chi0_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
     lib.chi0_census.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, ctypes.POINTER(ctypes.c_uint64)]
+    lib.chi0_plan_list.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Desc), ctypes.POINTER(_TetraList), vp, vp, vp]
+    lib.chi0_static_group.argtypes = [vp, i32, i32, ctypes.POINTER(_Q), vp, sz, vp]
+    lib.chi0_dynamic_group.argtypes = [vp, i32, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.chi0_iw_cubic.argtypes = [i32, i64p, i64p, ctypes.POINTER(ctypes.c_double), vp, vp, vp]
     lib.chi0_destroy.argtypes = [vp]
     lib.chi0_status_string.argtypes = [i32]
     lib.chi0_status_string.restype = ctypes.c_char_p
@@ -113,7 +124,8 @@ def load_library(path: str = LIB_PATH):
                  "chi0_kk_workspace_size", "chi0_dynamic_kk",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                  "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
-                 "chi0_batch_tune", "chi0_batch_info_get", "chi0_batch_destroy"):
+                 "chi0_batch_tune", "chi0_batch_info_get", "chi0_batch_destroy", "chi0_plan_list",
+                 "chi0_static_group", "chi0_dynamic_group", "chi0_iw_cubic"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -163,23 +175,38 @@ def _q_struct(q: "Q", dst: _Q):
 
 
 class Chi0Plan:
-    """A chi0 plan over fixed mesh band data (eps_k [nb][Nk], c_k [Nk][no][nb] on the device)."""
+    """A chi0 plan over fixed mesh band data (eps_k [nb][Nk], c_k [Nk][no][nb] on the device).
+
+    With tetrahedra=(tets, volume) the plan integrates over that explicit list instead of the
+    mesh's Kuhn tetrahedra (tets: int32 device tensor [n_tet][4] of corner indices into the
+    k-points of eps_k [nb][n_kp]; volume: zone fraction of one tetrahedron); nk is then unused
+    and every q must carry explicit k+q data."""
 
     def __init__(self, nk, eps_k, c_k=None, *, mu: float = 0.0, spin_factor: float = 2.0,
                  band_lo: int = 0, band_hi: int = 0, cma: bool = False, form: int = 0,
-                 precision: int = 0, stream=None):
+                 precision: int = 0, stream=None, tetrahedra=None):
         import torch
         self._lib = load_library()
-        self.nk = tuple(int(v) for v in nk)
         self.eps_k = eps_k
         self.c_k = c_k
+        if tetrahedra is not None:
+            nk = (int(eps_k.shape[1]), 1, 1)
+        self.nk = tuple(int(v) for v in nk)
         d = _make_desc(self.nk, eps_k, c_k, mu, spin_factor, band_lo, band_hi, cma, form, precision)
         self.nbw = (d.n_bands if band_hi <= 0 else band_hi) - band_lo
         self.cma = bool(cma)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
-        st = self._lib.chi0_plan(ctypes.byref(handle), ctypes.byref(d), _dev_ptr(eps_k, "torch.float64"),
-                                 _dev_ptr(c_k, "torch.complex128"), ctypes.c_void_p(self._stream.cuda_stream))
+        if tetrahedra is None:
+            st = self._lib.chi0_plan(ctypes.byref(handle), ctypes.byref(d), _dev_ptr(eps_k, "torch.float64"),
+                                     _dev_ptr(c_k, "torch.complex128"), ctypes.c_void_p(self._stream.cuda_stream))
+        else:
+            tets, volume = tetrahedra
+            self._tets = tets
+            tl = _TetraList(int(eps_k.shape[1]), int(tets.shape[0]), _dev_ptr(tets, "torch.int32"), float(volume))
+            st = self._lib.chi0_plan_list(ctypes.byref(handle), ctypes.byref(d), ctypes.byref(tl),
+                                          _dev_ptr(eps_k, "torch.float64"), _dev_ptr(c_k, "torch.complex128"),
+                                          ctypes.c_void_p(self._stream.cuda_stream))
         if st != 0:
             raise Chi0Error(st, "chi0_plan rejected the description")
         self._h = handle
@@ -251,6 +278,35 @@ class Chi0Plan:
         self._check(st, "chi0_dynamic")
         return torch.view_as_complex(chi)
 
+    def static_group(self, qs: Sequence[Q], n_group: int, workspace=None, out=None):
+        """Point-group loop, static: qs holds groups of n_group entries; float64 tensor
+        [len(qs) // n_group] of the per-group sums of Re chi0(q, 0)."""
+        import torch
+        if n_group < 1 or len(qs) % n_group:
+            raise ValueError("len(qs) must be a multiple of n_group")
+        nq = len(qs) // n_group
+        ws = workspace if workspace is not None else self.workspace(len(qs), 1)
+        chi = out if out is not None else torch.empty(nq, dtype=torch.float64, device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_static_group(self._h, nq, int(n_group), arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_static_group")
+        return chi
+
+    def dynamic_group(self, qs: Sequence[Q], n_group: int, omega, workspace=None, out=None):
+        """Point-group loop, dynamic: per-group sums of chi0(q, w), complex128 tensor [nq, nw]."""
+        import torch
+        if n_group < 1 or len(qs) % n_group:
+            raise ValueError("len(qs) must be a multiple of n_group")
+        nq, nw = len(qs) // n_group, int(omega.shape[0])
+        ws = workspace if workspace is not None else self.workspace(len(qs), nw)
+        chi = out if out is not None else torch.empty((nq, nw, 2), dtype=torch.float64, device=self.eps_k.device)
+        arr = self._qarray(qs)
+        st = self._lib.chi0_dynamic_group(self._h, nq, int(n_group), arr, nw, _dev_ptr(omega, "torch.float64"),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(chi.data_ptr()))
+        self._check(st, "chi0_dynamic_group")
+        return torch.view_as_complex(chi)
+
     def dynamic_kk(self, qs: Sequence[Q], omega, n_spec: int, spec_lo: float, spec_hi: float, workspace=None,
                    out=None):
         """chi0(q, w) by the Kramers-Kronig route: Im exact, Re from Im on the uniform spectral grid
@@ -303,6 +359,27 @@ class Chi0Plan:
         self._check(st, "chi0_census")
         return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
                 "near_evals": int(counts[2]), "far_evals": int(counts[3]), "far_terms": int(counts[4])}
+
+
+def iw_cubic(n: int):
+    """The irreducible wedge of a Gamma-centred n^3 simple-cubic mesh under O_h in tetrahedra
+    (host arrays from chi0_iw_cubic): (kfrac float64 [n_kp][3], tets int32 [n_tet][4],
+    volume of one tetrahedron, ops int32 [48][3][3])."""
+    import numpy as np
+    lib = load_library()
+    n_kp, n_tet, vol = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    st = lib.chi0_iw_cubic(int(n), ctypes.byref(n_kp), ctypes.byref(n_tet), ctypes.byref(vol), None, None, None)
+    if st != 0:
+        raise Chi0Error(st, f"chi0_iw_cubic({n})")
+    kfrac = np.zeros((n_kp.value, 3))
+    tets = np.zeros((n_tet.value, 4), dtype=np.int32)
+    ops = np.zeros((48, 3, 3), dtype=np.int32)
+    st = lib.chi0_iw_cubic(int(n), ctypes.byref(n_kp), ctypes.byref(n_tet), ctypes.byref(vol),
+                           kfrac.ctypes.data_as(ctypes.c_void_p), tets.ctypes.data_as(ctypes.c_void_p),
+                           ops.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise Chi0Error(st, f"chi0_iw_cubic({n})")
+    return kfrac, tets, vol.value, ops
 
 
 @dataclass

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchi0.so")
-SOURCES = ["k_tetra.hip", "k_contract.hip", "k_reduce.hip", "k_kk.hip", "chi0_api.cpp", "chi0_batch.cpp"]
+SOURCES = ["k_tetra.hip", "k_contract.hip", "k_reduce.hip", "k_kk.hip", "chi0_api.cpp", "chi0_batch.cpp",
+           "chi0_iw.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -29,6 +30,8 @@ struct TimedLaunch {
 struct chi0_plan_s {
     chi0_desc d;
     MeshDev mesh;
+    bool list = false;      // tetrahedron-list plan: explicit q only, prefactor spin_factor * volume
+    double volume = 0.0;
     hipStream_t stream;
     std::string err;
     bool profiling = false;
@@ -57,7 +60,13 @@ chi0_status device_fail(chi0_plan_t p, hipError_t e, const char *where)
 
 int64_t n_units(const chi0_plan_s *p)
 {
-    return 6 * p->mesh.nk * (int64_t)p->mesh.nbw * p->mesh.nbw;
+    return tets_per_pair(p->mesh) * p->mesh.nbw * p->mesh.nbw;
+}
+
+// Prefactor of the tetrahedron sum: g_s times the zone fraction of one tetrahedron.
+double prefactor(const chi0_plan_s *p)
+{
+    return p->list ? p->d.spin_factor * p->volume : p->d.spin_factor / (6.0 * (double)p->mesh.nk);
 }
 
 // Workgroups per q: up to 1024, each taking at least 4 rounds of 64 units.
@@ -70,7 +79,7 @@ int n_blocks(const chi0_plan_s *p)
 // Workgroups per band pair of the pair-resolved static call: up to 64, each at least 4 rounds.
 int n_blocks_pair(const chi0_plan_s *p)
 {
-    const int64_t rounds = (6 * p->mesh.nk + kWave - 1) / kWave;
+    const int64_t rounds = (tets_per_pair(p->mesh) + kWave - 1) / kWave;
     return (int)std::max<int64_t>(1, std::min<int64_t>(64, (rounds + 3) / 4));
 }
 
@@ -125,8 +134,34 @@ chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
         const char *msg = "";
         const chi0_status st = check_q(p->d, qs[i], &msg);
         if (st) return fail(p, st, msg);
+        if (p->list && !qs[i].explicit_kq)
+            return fail(p, CHI0_E_INVALID_ARG, "a tetrahedron-list plan takes explicit k+q data only");
     }
     return CHI0_OK;
+}
+
+// Launches of a group call: entries [e0, e0 + ne) of groups [g0, g0 + ng); a group of more than
+// kMaxQBatch entries is split over launches whose results are added to the first one's.
+struct GroupLaunch {
+    int e0, ne, g0, ng;
+    bool accumulate;
+};
+
+std::vector<GroupLaunch> group_launches(int nq, int n_group)
+{
+    std::vector<GroupLaunch> out;
+    if (n_group <= kMaxQBatch) {
+        const int per = kMaxQBatch / n_group;
+        for (int g0 = 0; g0 < nq; g0 += per) {
+            const int ng = std::min(per, nq - g0);
+            out.push_back({g0 * n_group, ng * n_group, g0, ng, false});
+        }
+    } else {
+        for (int g = 0; g < nq; ++g)
+            for (int c0 = 0; c0 < n_group; c0 += kMaxQBatch)
+                out.push_back({g * n_group + c0, std::min(kMaxQBatch, n_group - c0), g, 1, c0 > 0});
+    }
+    return out;
 }
 
 void fill_batch(const chi0_plan_s *p, const chi0_q *qs, int q0, int nqb, void *ws, const Layout &L, BatchDev &B)
@@ -202,6 +237,9 @@ MeshDev make_mesh(const chi0_desc &d, const double *eps_k, const double *c_k)
     M.mu = d.mu;
     M.eps_k = eps_k;
     M.c_k = c_k;
+    M.ncell = M.nk;
+    M.nperm = 6;
+    M.tets = nullptr;
     return M;
 }
 
@@ -274,6 +312,45 @@ chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *d, const double *eps_k,
     p->mesh = make_mesh(*d, eps_k, c_k);
     p->d.band_hi = p->mesh.lo + p->mesh.nbw;
     p->stream = static_cast<hipStream_t>(stream);
+    *out = p;
+    return CHI0_OK;
+}
+
+chi0_status chi0_plan_list(chi0_plan_t *out, const chi0_desc *d, const chi0_tetra_list *list, const double *eps_k,
+                           const double *c_k, void *stream)
+{
+    if (!out) return CHI0_E_INVALID_ARG;
+    *out = nullptr;
+    if (!d || !list || !list->tets) return CHI0_E_INVALID_ARG;
+    if (list->n_kp < 1 || list->n_kp >= (int64_t(1) << 31) || list->n_tet < 1 || list->n_tet >= (int64_t(1) << 31))
+        return CHI0_E_SHAPE;
+    if (!(list->volume > 0.0) || !std::isfinite(list->volume)) return CHI0_E_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(list->tets) % 16 != 0) return CHI0_E_INVALID_ARG;
+    // the band arrays are a one-dimensional "mesh" of n_kp points
+    chi0_desc dl = *d;
+    dl.nk[0] = (int32_t)list->n_kp;
+    dl.nk[1] = dl.nk[2] = 1;
+    const chi0_status st = check_desc(&dl, eps_k, c_k);
+    if (st) return st;
+    // every corner index must address a k-point: checked once on the host
+    std::vector<int32_t> h((size_t)list->n_tet * 4);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(h.data(), list->tets, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, hs) != hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return CHI0_E_DEVICE;
+    for (int32_t v : h)
+        if (v < 0 || v >= list->n_kp) return CHI0_E_SHAPE;
+    chi0_plan_s *p = new (std::nothrow) chi0_plan_s();
+    if (!p) return CHI0_E_INVALID_ARG;
+    p->d = dl;
+    p->mesh = make_mesh(dl, eps_k, c_k);
+    p->mesh.ncell = list->n_tet;
+    p->mesh.nperm = 1;
+    p->mesh.tets = list->tets;
+    p->list = true;
+    p->volume = list->volume;
+    p->d.band_hi = p->mesh.lo + p->mesh.nbw;
+    p->stream = hs;
     *out = p;
     return CHI0_OK;
 }
@@ -368,7 +445,7 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
-    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    const double scale = prefactor(p);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
@@ -398,7 +475,7 @@ chi0_status chi0_static_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, void 
     const int nblk = n_blocks_pair(p);
     const int npairs = p->mesh.nbw * p->mesh.nbw;
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
-    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    const double scale = prefactor(p);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
@@ -432,7 +509,7 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
-    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    const double scale = prefactor(p);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
@@ -487,7 +564,7 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
     double *im_all = reinterpret_cast<double *>(base + L.im_off);
     const double h = (spec_hi - spec_lo) / (double)(n_spec - 1);
     const int nblk = n_blocks(p);
-    const double scale = p->d.spin_factor / (6.0 * (double)p->mesh.nk);
+    const double scale = prefactor(p);
     hipError_t e = launch_kk_grid(spec_lo, h, n_spec, omega, nw, om_all, p->stream);
     if (e != hipSuccess) return device_fail(p, e, "frequency grid kernel");
     Layout Lw = {};   // W of the batch sits at the start of the workspace, as for chi0_dynamic
@@ -515,6 +592,83 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
         if ((e = launch_kk_transform(im_all, nqb, n_spec, nw, spec_lo, h, omega, chi + (int64_t)q0 * nw * 2,
                                      2 * (int64_t)nw, p->stream)) != hipSuccess)
             return device_fail(p, e, "Kramers-Kronig kernel");
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_static_group(chi0_plan_t p, int32_t nq, int32_t n_group, const chi0_q *qs, void *ws,
+                              size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || n_group < 1 || (int64_t)nq * n_group >= (int64_t(1) << 31))
+        return fail(p, CHI0_E_INVALID_ARG, "nq and n_group must be >= 1");
+    const int ne = nq * n_group;
+    chi0_status st = check_qs(p, ne, qs);
+    if (st) return st;
+    if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
+    const Layout L = layout(p, ne, 1);
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const int nblk = n_blocks(p);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = prefactor(p);
+    for (const GroupLaunch &G : group_launches(nq, n_group)) {
+        BatchDev B;
+        fill_batch(p, qs, G.e0, G.ne, ws, L, B);
+        const int per_group = G.ne / G.ng;
+        hipError_t e;
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, G.ne, p->d.precision, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, G.ne, nblk, partial, p->stream); })) !=
+            hipSuccess)
+            return device_fail(p, e, "tetrahedron kernel");
+        if ((e = timed(p, 2, [&] {
+                 return launch_reduce(partial, G.ng, per_group * nblk, 1, scale, chi + G.g0, 1, p->stream,
+                                      G.accumulate);
+             })) != hipSuccess)
+            return device_fail(p, e, "reduce kernel");
+    }
+    return CHI0_OK;
+}
+
+chi0_status chi0_dynamic_group(chi0_plan_t p, int32_t nq, int32_t n_group, const chi0_q *qs, int32_t nw,
+                               const double *omega, void *ws, size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || n_group < 1 || (int64_t)nq * n_group >= (int64_t(1) << 31))
+        return fail(p, CHI0_E_INVALID_ARG, "nq and n_group must be >= 1");
+    const int ne = nq * n_group;
+    chi0_status st = check_qs(p, ne, qs);
+    if (st) return st;
+    if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
+    const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
+    const Layout L = layout(p, ne, 2 * nwc_max);
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const int nblk = n_blocks(p);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = prefactor(p);
+    for (const GroupLaunch &G : group_launches(nq, n_group)) {
+        BatchDev B;
+        fill_batch(p, qs, G.e0, G.ne, ws, L, B);
+        const int per_group = G.ne / G.ng;
+        hipError_t e;
+        if (!p->d.cma &&
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, G.ne, p->d.precision, p->stream); })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
+            const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
+            if ((e = timed(p, 1, [&] {
+                     return launch_tetra_dynamic(p->mesh, B, G.ne, nblk, omega + w0, nwc, partial, p->d.precision != 0,
+                                                 p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "tetrahedron kernel");
+            if ((e = timed(p, 2, [&] {
+                     return launch_reduce(partial, G.ng, per_group * nblk, 2 * nwc, scale,
+                                          chi + ((int64_t)G.g0 * nw + w0) * 2, (int64_t)nw * 2, p->stream,
+                                          G.accumulate);
+                 })) != hipSuccess)
+                return device_fail(p, e, "reduce kernel");
+        }
     }
     return CHI0_OK;
 }

@@ -123,7 +123,7 @@ Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64
     double total_cost = 0.0;
     for (int i = 0; i < (int)inst.size(); ++i) {
         const MeshDev &M = inst[i].mesh;
-        const int64_t units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+        const int64_t units = tets_per_pair(M) * M.nbw * M.nbw;
         const int64_t rounds = (units + kWave - 1) / kWave;
         for (int j = 0; j < inst[i].in.nq; ++j) {
             Group g;

@@ -32,11 +32,20 @@ struct MeshDev {
     int32_t n1, n2, n3;
     int32_t nb, no, lo, nbw;
     int32_t cma, form;
-    int64_t nk;
+    int64_t nk;             // k-points of the arrays (the mesh, or the points of a tetrahedron list)
     double mu;
     const double *eps_k;    // [nb][Nk]
     const double *c_k;      // [Nk][no][nb] complex
+    // Tetrahedra per band pair = nperm * ncell: the mesh's 6 Kuhn tetrahedra per cell (nperm 6,
+    // ncell Nk, tets null) or an explicit list (nperm 1, ncell n_tet, tets [n_tet][4] corner
+    // indices into the k-points).
+    int64_t ncell;
+    int32_t nperm;
+    const int32_t *tets;
 };
+
+// Tetrahedra per band pair.
+__host__ __device__ inline int64_t tets_per_pair(const MeshDev &M) { return (int64_t)M.nperm * M.ncell; }
 
 // One (instance, q) item of a fused batch launch (device table entry).
 struct BatchItemDev {
@@ -101,6 +110,6 @@ hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, con
 
 // K_R: out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], fixed order.
 hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale,
-                         double *out, int64_t out_stride, hipStream_t s);
+                         double *out, int64_t out_stride, hipStream_t s, bool accumulate = false);
 
 }  // namespace chi0

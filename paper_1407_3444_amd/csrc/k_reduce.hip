@@ -1,6 +1,8 @@
 // k_reduce.hip -- deterministic final reduction (K_R).
 // out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], with the
-// blocks added in increasing order, so repeated runs give bitwise-identical chi0.
+// blocks added in increasing order, so repeated runs give bitwise-identical chi0.  A sum over
+// a group of q-entries (the point-group loop) is the same sum over the group's consecutive
+// blocks, added to the earlier launches' result when a group spans several launches.
 #include "chi0_internal.h"
 
 namespace chi0 {
@@ -32,13 +34,18 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const BatchItemDev *_
     it.out[v] = it.scale * ordered_sum(it.partial + v, it.nblocks, nvals);
 }
 
+// accumulate: add to what out holds (the earlier parts of a sum split over launches) instead of
+// overwriting it.
 __global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int nblocks, int nvals,
-                                                     double scale, double *__restrict__ out, int64_t out_stride)
+                                                     double scale, double *__restrict__ out, int64_t out_stride,
+                                                     int accumulate)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (v >= nvals) return;
-    out[(int64_t)q * out_stride + v] = scale * ordered_sum(partial + (int64_t)q * nblocks * nvals + v, nblocks, nvals);
+    const double s = scale * ordered_sum(partial + (int64_t)q * nblocks * nvals + v, nblocks, nvals);
+    double *o = out + (int64_t)q * out_stride + v;
+    *o = accumulate ? *o + s : s;
 }
 
 }  // namespace
@@ -52,11 +59,12 @@ hipError_t launch_reduce_batch(const BatchItemDev *items, const int32_t *block_i
 }
 
 hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale, double *out,
-                         int64_t out_stride, hipStream_t s)
+                         int64_t out_stride, hipStream_t s, bool accumulate)
 {
     if (nq < 1 || nblocks < 1 || nvals < 1) return hipErrorInvalidValue;
     dim3 grid((nvals + 255) / 256, nq), block(256);
-    hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, partial, nblocks, nvals, scale, out, out_stride);
+    hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, partial, nblocks, nvals, scale, out, out_stride,
+                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -55,32 +55,44 @@ constexpr int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 
 // Corner values of unit u (pair-major, then tetrahedron permutation, then cell).
-// A unit = (band pair, tetrahedron of a cell, cell): unit index u = (pair * 6 + perm) * Nk + cell.
+// A unit = (band pair, tetrahedron of a cell, cell): unit index u = (pair * nperm + perm) * ncell + cell;
+// a tetrahedron list is one "permutation" whose cells are the listed tetrahedra.
 struct UnitIdx {
     int pair, perm, cell;
 };
 
+// Tetrahedra of a cell: the 6 Kuhn tetrahedra of a mesh cell, or one listed tetrahedron
+// (LIST: the kernels are compiled for mesh plans and list plans separately, so the mesh path
+// carries nothing of the list path).
+template <bool LIST>
+__device__ __forceinline__ int64_t n_cells(const MeshDev &M) { return LIST ? M.ncell : M.nk; }
+template <bool LIST>
+constexpr int n_perm() { return LIST ? 1 : 6; }
+
 // General decomposition of a unit index (64-bit divisions).
+template <bool LIST>
 __device__ __forceinline__ UnitIdx decode_unit(const MeshDev &M, int64_t u)
 {
     UnitIdx x;
-    const int64_t q = u / M.nk;
-    x.cell = (int)(u - q * M.nk);
-    x.pair = (int)(q / 6);
-    x.perm = (int)(q - (int64_t)x.pair * 6);
+    const int64_t nc = n_cells<LIST>(M);
+    const int64_t q = u / nc;
+    x.cell = (int)(u - q * nc);
+    x.pair = (int)(q / n_perm<LIST>());
+    x.perm = (int)(q - (int64_t)x.pair * n_perm<LIST>());
     return x;
 }
 
 // Unit base + lane of a round of 64 consecutive units: the round's base is decomposed once
 // (wave-uniform, scalar arithmetic) and every lane carries its offset into the cell index.
+template <bool LIST>
 __device__ __forceinline__ UnitIdx round_unit(const MeshDev &M, const UnitIdx &b, int lane)
 {
     UnitIdx x = b;
     x.cell += lane;
-    const int nk = (int)M.nk;
-    while (x.cell >= nk) {        // at most once unless the mesh has fewer than 64 points
-        x.cell -= nk;
-        if (++x.perm == 6) {
+    const int nc = (int)n_cells<LIST>(M);
+    while (x.cell >= nc) {        // at most once unless there are fewer than 64 cells
+        x.cell -= nc;
+        if (++x.perm == n_perm<LIST>()) {
             x.perm = 0;
             ++x.pair;
         }
@@ -88,20 +100,37 @@ __device__ __forceinline__ UnitIdx round_unit(const MeshDev &M, const UnitIdx &b
     return x;
 }
 
+template <bool LIST>
 __device__ __forceinline__ void load_unit(const MeshDev &M, const QDev &Q, const UnitIdx &x, Vtx t[4])
 {
     const int64_t nk = M.nk;
     const int pair = x.pair, perm = x.perm;
     const int n = pair / M.nbw, m = pair - n * M.nbw;
+    const double *ek = M.eps_k + (int64_t)(M.lo + n) * nk;
+    const double *ekq = Q.eps_kq + (int64_t)(M.lo + m) * nk;
+    const double *Wp = M.cma ? nullptr : Q.W + (int64_t)pair * nk;
+    auto put = [&](int c, int64_t idx, int64_t idq) {
+        const double e = ek[idx], ep = ekq[idq];
+        t[c].a = e - M.mu;
+        t[c].b = ep - M.mu;
+        t[c].D = ep - e;
+        t[c].W = M.cma ? 1.0 : Wp[idx];
+    };
+    if (LIST) {
+        // explicit tetrahedron (list plans): corner k-points from the list, k+q data at the same points
+        const int4 c4 = reinterpret_cast<const int4 *>(M.tets)[x.cell];
+        put(0, c4.x, c4.x);
+        put(1, c4.y, c4.y);
+        put(2, c4.z, c4.z);
+        put(3, c4.w, c4.w);
+        return;
+    }
     int i[3];
     const unsigned c12 = (unsigned)x.cell / (unsigned)M.n3;
     i[2] = x.cell - (int)(c12 * (unsigned)M.n3);
     i[0] = (int)(c12 / (unsigned)M.n2);
     i[1] = (int)c12 - i[0] * M.n2;
     const int nn[3] = {M.n1, M.n2, M.n3};
-    const double *ek = M.eps_k + (int64_t)(M.lo + n) * nk;
-    const double *ekq = Q.eps_kq + (int64_t)(M.lo + m) * nk;
-    const double *Wp = M.cma ? nullptr : Q.W + (int64_t)pair * nk;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         if (c > 0) {
@@ -117,11 +146,7 @@ __device__ __forceinline__ void load_unit(const MeshDev &M, const QDev &Q, const
             j2 -= j2 >= M.n3 ? M.n3 : 0;
             idq = ((int64_t)j0 * M.n2 + j1) * M.n3 + j2;
         }
-        const double e = ek[idx], ep = ekq[idq];
-        t[c].a = e - M.mu;
-        t[c].b = ep - M.mu;
-        t[c].D = ep - e;
-        t[c].W = M.cma ? 1.0 : Wp[idx];
+        put(c, idx, idq);
     }
 }
 
@@ -212,7 +237,7 @@ __device__ __forceinline__ int wave_inclusive_scan(int x, int lane)
 // Returns the number of records; next_out receives the first lane left for a later pass.
 // The unit's corner values are loaded again here (cache hits) rather than kept in
 // registers across the evaluation of the list.
-template <class Rec, int CAP>
+template <class Rec, int CAP, bool LIST>
 __device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, const UnitIdx &ux, bool valid, int cnt,
                                          int start, int lane, Rec *list, int &next_out)
 {
@@ -225,7 +250,7 @@ __device__ __forceinline__ int fill_list(const MeshDev &M, const QDev &Q, const 
     const int nrec = __shfl(incl, next - 1, kWave);
     if (fits && valid && cnt > 0) {
         Vtx t[4];
-        load_unit(M, Q, ux, t);
+        load_unit<LIST>(M, Q, ux, t);
         write_unit<Rec>(t, M.form, list, excl, incl);
     }
     next_out = next;
@@ -306,13 +331,13 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
 
 // One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
 // partial sums for every frequency to part[nw][2].
-template <int NSLOT, bool MIXED>
+template <int NSLOT, bool MIXED, bool LIST>
 __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, int nblocks, int blk,
                                              const double *__restrict__ omega, int nw, double *__restrict__ part,
                                              DynRec *list, uint16_t (*queue)[kWave])
 {
     const int lane = threadIdx.x;
-    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
 
     // frequencies of this lane (slot s holds w[lane + 64 s]; dead lanes repeat the last one)
     // and their interval [wlo, whi] over the wave, from which each tetrahedron's far-series
@@ -337,18 +362,18 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
     // samples all band pairs, so the work per workgroup is even
     for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
         const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
-            load_unit(M, Q, ux, t);
+            load_unit<LIST>(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<DynRec, kCapDyn>(M, Q, ux, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<DynRec, kCapDyn, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -471,7 +496,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     }
 }
 
-template <int NSLOT, bool MIXED>
+template <int NSLOT, bool MIXED, bool LIST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_dynamic_kernel(MeshDev M, BatchDev B, int nblocks,
                                                            const double *__restrict__ omega, int nw,
                                                            double *__restrict__ partial)
@@ -479,7 +504,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
     __shared__ DynRec list[kCapDyn];
     __shared__ uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
-    dynamic_body<NSLOT, MIXED>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
+    dynamic_body<NSLOT, MIXED, LIST>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
                                partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue);
 }
 
@@ -497,10 +522,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
     switch (slots * 2 + (it.precision != 0 ? 1 : 0)) {
 #define C0_CASE(S)                                                                                        \
     case 2 * S:                                                                                           \
-        dynamic_body<S, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);          \
+        dynamic_body<S, false, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);          \
         break;                                                                                            \
     case 2 * S + 1:                                                                                       \
-        dynamic_body<S, true>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);           \
+        dynamic_body<S, true, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);           \
         break;
         C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
 #undef C0_CASE
@@ -511,24 +536,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
 // Static evaluation (w = 0, Re only) of units [u0, u1) by workgroup blk of nblocks: rounds of
 // 64 consecutive units dealt round-robin; each lane evaluates its own final tetrahedra.
 // Returns the workgroup's sum (valid in every lane).
+template <bool LIST>
 __device__ __forceinline__ double static_body(const MeshDev &M, const QDev &Q, int64_t u0, int64_t u1, int blk,
                                               int nblocks, StatRec *list)
 {
     const int lane = threadIdx.x;
     double acc = 0.0;
     for (int64_t base = u0 + (int64_t)blk * kWave; base < u1; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
         const bool valid = base + lane < u1;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
-            load_unit(M, Q, ux, t);
+            load_unit<LIST>(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<StatRec, kCapStat>(M, Q, ux, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<StatRec, kCapStat, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -545,13 +571,14 @@ __device__ __forceinline__ double static_body(const MeshDev &M, const QDev &Q, i
     return acc;
 }
 
+template <bool LIST>
 __global__ __launch_bounds__(64) void tetra_static_kernel(MeshDev M, BatchDev B, int nblocks,
                                                           double *__restrict__ partial)
 {
     __shared__ StatRec list[kCapStat];
     const int qi = blockIdx.y;
-    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
-    const double acc = static_body(M, B.q[qi], 0, n_units, blockIdx.x, nblocks, list);
+    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
+    const double acc = static_body<LIST>(M, B.q[qi], 0, n_units, blockIdx.x, nblocks, list);
     if (threadIdx.x == 0) partial[(int64_t)qi * nblocks + blockIdx.x] = acc;
 }
 
@@ -586,7 +613,7 @@ __device__ __forceinline__ void drain_im(const ImRec *list, uint16_t (*queue)[kW
     }
 }
 
-template <int NSLOT>
+template <int NSLOT, bool LIST>
 __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int nblocks,
                                                       const double *__restrict__ omega, int nw,
                                                       double *__restrict__ partial)
@@ -597,7 +624,7 @@ __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int
     const QDev Q = B.q[qi];
     const int lane = threadIdx.x;
     const int blk = blockIdx.x;
-    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
     double om[NSLOT], acc[NSLOT];
     bool live[NSLOT];
     double wlo = omega[nw - 1], whi = wlo;
@@ -614,18 +641,18 @@ __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int
     whi = wave_max(whi);
     int qn = 0;
     for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit(M, decode_unit(M, base), lane);
+        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
         const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
             Vtx t[4];
-            load_unit(M, Q, ux, t);
+            load_unit<LIST>(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<ImRec, kCapIm>(M, Q, ux, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<ImRec, kCapIm, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             __syncthreads();
@@ -666,7 +693,8 @@ __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int
 }
 
 // Band-pair resolved static evaluation: workgroup x = p * nblk + j takes the units of pair p
-// (6 Nk consecutive units) as part j of nblk; partial[q][j][pair].
+// (its tetrahedra: consecutive units) as part j of nblk; partial[q][j][pair].
+template <bool LIST>
 __global__ __launch_bounds__(64) void tetra_static_pairs_kernel(MeshDev M, BatchDev B, int nblk,
                                                                 double *__restrict__ partial)
 {
@@ -674,8 +702,8 @@ __global__ __launch_bounds__(64) void tetra_static_pairs_kernel(MeshDev M, Batch
     const int qi = blockIdx.y;
     const int npairs = M.nbw * M.nbw;
     const int p = blockIdx.x / nblk, j = blockIdx.x - p * nblk;
-    const int64_t per_pair = 6 * M.nk;
-    const double acc = static_body(M, B.q[qi], (int64_t)p * per_pair, (int64_t)(p + 1) * per_pair, j, nblk, list);
+    const int64_t per_pair = tets_per_pair(M);
+    const double acc = static_body<LIST>(M, B.q[qi], (int64_t)p * per_pair, (int64_t)(p + 1) * per_pair, j, nblk, list);
     if (threadIdx.x == 0) partial[((int64_t)qi * nblk + j) * npairs + p] = acc;
 }
 
@@ -713,6 +741,7 @@ struct CensusSink {
     }
 };
 
+template <bool LIST>
 __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, const double *__restrict__ omega, int nw,
                                                      int step, int first_chunk,
                                                      unsigned long long *__restrict__ counts)
@@ -724,7 +753,7 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
     }
     const int qi = blockIdx.y;
     const QDev Q = B.q[qi];
-    const int64_t n_units = 6 * M.nk * (int64_t)M.nbw * M.nbw;
+    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
     CensusSink cs;
     cs.omega = omega;
     cs.wlo = wlo;
@@ -737,7 +766,7 @@ __global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, cons
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
          u += (int64_t)gridDim.x * blockDim.x) {
         Vtx t[4];
-        load_unit(M, Q, decode_unit(M, u), t);
+        load_unit<LIST>(M, Q, decode_unit<LIST>(M, u), t);
         const unsigned long long before = cs.n_tet;
         if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, cs);
         if (M.form == 0 && !region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
@@ -759,15 +788,35 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
 {
     if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
-    const int slots = (nw + kWave - 1) / kWave;
-    switch (slots * 2 + (mixed ? 1 : 0)) {
-#define C0_CASE(S)                                                                                        \
+    int slots = (nw + kWave - 1) / kWave;
+    if (mesh.tets) {
+        // list plans: slot counts 1, 2, 4, 8 (a kernel with more slots than frequencies idles the
+        // extra ones)
+        slots = slots <= 1 ? 1 : slots <= 2 ? 2 : slots <= 4 ? 4 : 8;
+        switch (slots * 2 + (mixed ? 1 : 0)) {
+#define C0_LIST(S)                                                                                        \
     case 2 * S:                                                                                           \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false>), grid, block, 0, s, mesh, batch, nblocks,     \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false, true>), grid, block, 0, s, mesh, batch, nblocks, \
                            omega, nw, partial);                                                           \
         break;                                                                                            \
     case 2 * S + 1:                                                                                       \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true>), grid, block, 0, s, mesh, batch, nblocks,      \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true, true>), grid, block, 0, s, mesh, batch, nblocks,  \
+                           omega, nw, partial);                                                           \
+        break;
+            C0_LIST(1) C0_LIST(2) C0_LIST(4) C0_LIST(8)
+#undef C0_LIST
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (slots * 2 + (mixed ? 1 : 0)) {
+#define C0_CASE(S)                                                                                        \
+    case 2 * S:                                                                                           \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false, false>), grid, block, 0, s, mesh, batch, nblocks, \
+                           omega, nw, partial);                                                           \
+        break;                                                                                            \
+    case 2 * S + 1:                                                                                       \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true, false>), grid, block, 0, s, mesh, batch, nblocks,  \
                            omega, nw, partial);                                                           \
         break;
         C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
@@ -790,8 +839,12 @@ hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, con
     if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch) return hipErrorInvalidValue;
     dim3 grid(1024, nq), block(256);
     const int step = (mixed ? kFarTerms32 : kFarTerms) / kFarClasses;
-    hipLaunchKernelGGL(census_kernel, grid, block, 0, s, mesh, batch, omega, nw, step, first_chunk ? 1 : 0,
-                       counts);
+    if (mesh.tets)
+        hipLaunchKernelGGL(census_kernel<true>, grid, block, 0, s, mesh, batch, omega, nw, step,
+                           first_chunk ? 1 : 0, counts);
+    else
+        hipLaunchKernelGGL(census_kernel<false>, grid, block, 0, s, mesh, batch, omega, nw, step,
+                           first_chunk ? 1 : 0, counts);
     return hipGetLastError();
 }
 
@@ -800,10 +853,18 @@ hipError_t launch_tetra_im(const MeshDev &mesh, const BatchDev &batch, int nq, i
 {
     if (nw < 1 || nw > kMaxOmegaIm || nq < 1 || nq > kMaxQBatch || nblocks < 1) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
-    if (nw <= 8 * kWave)
-        hipLaunchKernelGGL(tetra_im_kernel<8>, grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
-    else
-        hipLaunchKernelGGL(tetra_im_kernel<16>, grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+    const bool list = mesh.tets != nullptr;
+    if (nw <= 8 * kWave) {
+        if (list)
+            hipLaunchKernelGGL((tetra_im_kernel<8, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+        else
+            hipLaunchKernelGGL((tetra_im_kernel<8, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+    } else {
+        if (list)
+            hipLaunchKernelGGL((tetra_im_kernel<16, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+        else
+            hipLaunchKernelGGL((tetra_im_kernel<16, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
+    }
     return hipGetLastError();
 }
 
@@ -812,7 +873,10 @@ hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch,
 {
     if (nq < 1 || nq > kMaxQBatch || nblk < 1) return hipErrorInvalidValue;
     dim3 grid(nblk * mesh.nbw * mesh.nbw, nq), block(kWave);
-    hipLaunchKernelGGL(tetra_static_pairs_kernel, grid, block, 0, s, mesh, batch, nblk, partial);
+    if (mesh.tets)
+        hipLaunchKernelGGL(tetra_static_pairs_kernel<true>, grid, block, 0, s, mesh, batch, nblk, partial);
+    else
+        hipLaunchKernelGGL(tetra_static_pairs_kernel<false>, grid, block, 0, s, mesh, batch, nblk, partial);
     return hipGetLastError();
 }
 
@@ -821,7 +885,10 @@ hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int n
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     dim3 grid(nblocks, nq), block(kWave);
-    hipLaunchKernelGGL(tetra_static_kernel, grid, block, 0, s, mesh, batch, nblocks, partial);
+    if (mesh.tets)
+        hipLaunchKernelGGL(tetra_static_kernel<true>, grid, block, 0, s, mesh, batch, nblocks, partial);
+    else
+        hipLaunchKernelGGL(tetra_static_kernel<false>, grid, block, 0, s, mesh, batch, nblocks, partial);
     return hipGetLastError();
 }
 

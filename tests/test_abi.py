@@ -200,3 +200,47 @@ def test_plane_wave_basis_sizes():
     assert _plan(_desc(n_orb=4096, n_bands=8))[0] == 0
     assert _plan(_desc(n_orb=16384, n_bands=8))[0] == 0
     assert _plan(_desc(n_orb=16385, n_bands=8))[0] == -2
+
+
+def test_iw_cubic_host_builder():
+    """The wedge builder is host code: sizes, the O_h matrices, and the same wedge as the oracle's
+    own construction (compared as sets of corner coordinates)."""
+    import numpy as np
+    import oracle
+    so = lib.load_library()
+    n_kp, n_tet, vol = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    for bad in (0, 3, 7, 1026):
+        assert so.chi0_iw_cubic(bad, ctypes.byref(n_kp), ctypes.byref(n_tet), ctypes.byref(vol), None, None,
+                                None) == -2
+    assert so.chi0_iw_cubic(8, None, ctypes.byref(n_tet), ctypes.byref(vol), None, None, None) == -1
+    for n in (2, 6, 12):
+        kf, tets, v, ops = lib.iw_cubic(n)
+        m = n // 2
+        assert kf.shape == ((m + 1) * (m + 2) * (m + 3) // 6, 3) and tets.shape == (m ** 3, 4)
+        assert v == 1.0 / (6 * n ** 3)
+        assert np.array_equal(ops[0], np.eye(3, dtype=np.int32))
+        assert len({g.tobytes() for g in ops}) == 48
+        for g in ops:
+            assert np.array_equal(g @ g.T, np.eye(3, dtype=np.int32))
+        kf2, tets2, v2 = oracle.iw_cubic(n)
+        key = lambda k, t: sorted(tuple(sorted(map(tuple, np.round(k[c] * n).astype(int)))) for c in t)
+        assert key(kf, tets) == key(kf2, tets2)
+
+
+def test_list_plan_validates_on_the_host():
+    so = lib.load_library()
+    d = _desc(cma=1)
+    h = ctypes.c_void_p()
+
+    def make(n_kp=5, n_tet=1, tets=4096, volume=0.1):
+        tl = lib._TetraList(n_kp, n_tet, tets, volume)
+        return so.chi0_plan_list(ctypes.byref(h), ctypes.byref(d), ctypes.byref(tl), FAKE, None, None)
+
+    assert make(n_kp=0) == -2
+    assert make(n_tet=0) == -2
+    assert make(n_kp=1 << 31) == -2
+    assert make(tets=None) == -1
+    assert make(tets=4100) == -1          # not 16-byte aligned
+    assert make(volume=0.0) == -1
+    assert make(volume=float("nan")) == -1
+    assert so.chi0_plan_list(ctypes.byref(h), ctypes.byref(d), None, FAKE, None, None) == -1
