@@ -15,7 +15,9 @@ region.  Prints one JSON line.
 64 q x 512 w, --n-keep band window), tetra_static (the 10-orbital model, 256 q, static),
 sc_cma (single-band cubic, 16^3, 8 q, static), batch (16 heterogeneous instances in one
 fused launch sequence) and pw_static (plane-wave basis: 4096 coefficients per band, 32 bands,
-12^3 mesh, 16 q, static; the matrix-element contraction against the FP64 MFMA roofline).
+12^3 mesh, 16 q, static; the matrix-element contraction against the FP64 MFMA roofline) and
+iw_cubic (the irreducible wedge of a 48^3 cubic mesh with the 48-element point-group loop, beside
+the full mesh at the same q).
 """
 from __future__ import annotations
 
@@ -254,6 +256,124 @@ def bench_pw(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_iw(args):
+    """Irreducible wedge with the point-group loop (Sec. II): a 6-orbital O_h-symmetric cubic model,
+    the wedge of the 48^3 mesh (13,824 tetrahedra, 2,925 points), 48 group elements per q, 4 q,
+    256 frequencies, dynamic, FP64; the full 48^3 Kuhn mesh at the same q is timed beside it (the
+    same number of tetrahedron units; the two triangulations differ, so the values agree to the
+    discretisation error)."""
+    import torch
+    import paper_1407_3444_amd as lib
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    n, nw = 48, 256
+    model = synth.cubic_s_model(5, 6)
+    q_list = [np.array(v) for v in ([0.1, 0.0, 0.0], [0.23, 0.0, 0.0], [0.1, 0.1, 0.0], [0.19, 0.07, 0.03])]
+    omega = synth.omega_grid(nw)
+    mu = 0.0
+    kf, tets, vol, ops = lib.iw_cubic(n)
+    e, c = synth.eigensystem(model, kf)
+    opsf = ops.astype(np.float64)
+    entries = []
+    for q in q_list:
+        for g in opsf:
+            entries.append(synth.eigensystem(model, kf + q @ g))
+    log(f"wedge inputs built in {time.time() - t0:.1f}s: {len(kf)} points, {len(tets)} tetrahedra, "
+        f"{len(entries)} (q, g) entries")
+    om = torch.from_numpy(omega).to(dev)
+    eps_d, c_d = torch.from_numpy(e).to(dev), torch.from_numpy(c).to(dev)
+    plan = lib.Chi0Plan(None, eps_d, c_d, mu=mu, tetrahedra=(torch.from_numpy(tets).to(dev), vol))
+    qs = [lib.Q(eps_kq=torch.from_numpy(a).to(dev), c_kq=torch.from_numpy(b).to(dev)) for a, b in entries]
+    ws = plan.workspace(len(qs), nw)
+    out = torch.empty((len(q_list), nw, 2), dtype=torch.float64, device=dev)
+    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0}
+    for i in range(0, len(qs), 16):
+        cz = plan.census(qs[i:i + 16], om, workspace=ws)
+        for k in census:
+            census[k] += cz[k]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    plan.profile(True)
+    plan.read_profile()
+    ms = timed(lambda: plan.dynamic_group(qs, 48, om, workspace=ws, out=out), args.steps)
+    prof = plan.read_profile()
+    plan.profile(False)
+    log(f"wedge + point-group loop: {ms:.1f} ms/step", prof)
+    got = torch.view_as_complex(out).cpu().numpy()
+
+    # the full Kuhn mesh at the same q (explicit k+q)
+    nk = (n, n, n)
+    kfm = synth.mesh_kfrac(nk)
+    em, cm = synth.eigensystem(model, kfm)
+    mplan = lib.Chi0Plan(nk, torch.from_numpy(em).to(dev), torch.from_numpy(cm).to(dev), mu=mu)
+    mqs = []
+    for q in q_list:
+        a, b = synth.eigensystem(model, kfm + q)
+        mqs.append(lib.Q(eps_kq=torch.from_numpy(a).to(dev), c_kq=torch.from_numpy(b).to(dev)))
+    mws = mplan.workspace(len(mqs), nw)
+    mout = torch.empty((len(q_list), nw, 2), dtype=torch.float64, device=dev)
+    mms = timed(lambda: mplan.dynamic(mqs, om, workspace=mws, out=mout), args.steps)
+    mesh_val = torch.view_as_complex(mout).cpu().numpy()
+    diff = float(np.max(np.abs(got - mesh_val)) / np.max(np.abs(mesh_val)))
+    log(f"full mesh: {mms:.1f} ms/step; wedge vs mesh max rel difference {diff:.2e}")
+
+    nbw = 6
+    units = len(entries) * len(tets) * nbw * nbw * nw
+    tet = prof["tetra"]
+    avg_ms = tet["ms"] / tet["launches"]
+    achieved = census_flops(census) / (tet["ms"] / args.steps * 1e-3) / 1e12
+    result = {"metric": METRIC, "value_form": VALUE_FORM, "value": units / (ms * 1e-3), "unit": "updates/s",
+              "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+              "data": "synthetic (seeded 6-orbital O_h-symmetric cubic tight-binding model)",
+              "config": {"workload": "irreducible wedge of a 48^3 simple-cubic mesh (13,824 tetrahedra) with the "
+                                     "48-element point-group loop, 6 orbitals (36 band pairs), 4 q x 256 w, dynamic, "
+                                     "FP64",
+                         "wedge_points": int(len(kf)), "wedge_tetrahedra": int(len(tets)), "group_order": 48,
+                         "n_q": len(q_list), "n_omega": nw, "units_per_step": units, "parallelism": "single GPU"},
+              "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                           "kernel": "tetra_dynamic_kernel (list form), all launches of a step",
+                           "avg_launch_ms": round(avg_ms, 3),
+                           "launches_per_step": tet["launches"] / args.steps},
+              "census": census,
+              "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
+              "full_mesh_same_q": {"ms_per_step": mms, "value": units / (mms * 1e-3),
+                                   "max_rel_difference_vs_wedge": diff}}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        sample_g, sample_w = list(range(0, 48, 4)), [0, 36, 73, 109, 146, 182, 219, 255]
+        t1 = time.time()
+        ref = oracle.chi0_iw(e, c, [entries[g] for g in sample_g], tets, vol, omega[sample_w], mu=mu,
+                             nthreads=threads)
+        dt = time.time() - t1
+        u = len(sample_g) * len(tets) * nbw * nbw * len(sample_w)
+        # parity on the same sample: the GPU sum over the same six group elements of q 0
+        sub = [qs[g] for g in sample_g]
+        part = plan.dynamic_group(sub, len(sub), om).cpu().numpy()[0][sample_w]
+        err = float(np.max(np.abs(part - ref)) / np.max(np.abs(ref)))
+        result["cpu_baseline"] = {"value": u / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+                                  "sample": f"q 0, {len(sample_g)} of 48 group elements, {len(sample_w)} w, "
+                                            f"{dt:.1f} s"}
+        result["parity_sample"] = {"max_rel_err_vs_oracle": err, "q": 0, "group_elements": sample_g,
+                                   "omega_index": sample_w}
+        log(f"oracle sample {dt:.1f}s, rel err {err:.2e}")
+    print(json.dumps(result), flush=True)
+
+
 def bench_batch(args):
     """The 16-instance heterogeneous batch: one fused, graph-captured launch sequence per step
     (FP64 and mixed), against the same instances as 16 sequential chi0_dynamic calls (FP64)."""
@@ -376,7 +496,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--workload", default="tetra_dynamic",
-                    choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma", "batch", "pw_static"])
+                    choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma", "batch", "pw_static",
+                             "iw_cubic"])
     ap.add_argument("--batch-nq-div", type=int, default=8,
                     help="batch workload: divide every instance's q count by this (1 = full size)")
     ap.add_argument("--batch-workgroups", type=int, default=0, help="batch workload: K_B workgroups (0 = default)")
@@ -411,6 +532,8 @@ def main():
         return bench_batch(args)
     if args.workload == "pw_static":
         return bench_pw(args)
+    if args.workload == "iw_cubic":
+        return bench_iw(args)
     if args.workload == "tetra_dynamic":
         wl = synth.make_workload("tetra_dynamic", nq=64, q_subset=list(range(min(args.nq, 64))),
                                  workers=args.workers)

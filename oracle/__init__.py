@@ -52,7 +52,7 @@ def _load():
         lib.chi0_oracle_carve.argtypes = [dp, dp, i, dp, dp]
         lib.chi0_oracle_carve.restype = i
         lib.chi0_oracle_list.argtypes = [i, i, i, dp, dp, dp, dp, ll, ctypes.POINTER(ctypes.c_int), d, d, d, i, i,
-                                         i, i, i, dp, i, dp]
+                                         i, i, i, i, dp, i, dp]
         lib.chi0_oracle_list.restype = i
         lib.chi0_oracle_tet_corners.argtypes = [i, i, i, ll, i, ctypes.POINTER(ctypes.c_longlong)]
         lib.chi0_oracle_tet_corners.restype = None
@@ -101,10 +101,11 @@ def chi0_raw(nk, eps_k, c_k, omega, *, eps_kq=None, c_kq=None, shift=(0, 0, 0), 
 
 
 def chi0_list(eps_k, c_k, eps_kq, c_kq, tets, volume: float, omega, *, mu=0.0, spin_factor=2.0, band_lo=0,
-              band_hi=-1, cma=False, form=0, nthreads: int = 0) -> np.ndarray:
+              band_hi=-1, cma=False, form=0, single_carving=False, nthreads: int = 0) -> np.ndarray:
     """chi0 at one q over an explicit list of tetrahedra (corner indices tets [n_tet][4] into the
     k-points of eps_k [nb][n_kp]; eps_kq/c_kq hold the data at the same points shifted by q; each
-    tetrahedron is the fraction `volume` of the zone): complex array [nw]."""
+    tetrahedron is the fraction `volume` of the zone): complex array [nw].  single_carving (form 1
+    only) is the comparison treatment without the second carving."""
     lib = _load()
     eps_k = _f64(eps_k)
     nb, n_kp = eps_k.shape
@@ -116,7 +117,7 @@ def chi0_list(eps_k, c_k, eps_kq, c_kq, tets, volume: float, omega, *, mu=0.0, s
     rc = lib.chi0_oracle_list(int(n_kp), nb, no, _ptr(eps_k), _ptr(ck), _ptr(_f64(eps_kq)), _ptr(ckq),
                               tets.shape[0], tets.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(volume),
                               float(mu), float(spin_factor), int(band_lo), int(band_hi), int(bool(cma)), int(form),
-                              omega.size, _ptr(omega), int(nthreads), _ptr(out))
+                              int(bool(single_carving)), omega.size, _ptr(omega), int(nthreads), _ptr(out))
     if rc != 0:
         raise ValueError("chi0_oracle_list failed with code %d" % rc)
     return out[:, 0] + 1j * out[:, 1]

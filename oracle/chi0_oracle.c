@@ -330,6 +330,7 @@ typedef struct {
     int shift[3];
     double mu;
     int cma, form;
+    int single_carving; /* comparison only: first carving alone (see tet_contribution_at) */
     double *W; /* [nbw][nbw][nk] */
 } problem;
 
@@ -413,6 +414,22 @@ static void tet_contribution_at(const problem *P, const long long idx[4], const 
             }
             cplx *pacc = acc + (size_t)(n * P->nbw + m) * pair_stride;
             btet S[9];
+            if (P->single_carving) {
+                /* The treatment the second carving replaces (Sec. II): only the occupied part
+                 * e < mu is carved out; the final-state factor Theta(e' - mu) is taken at the
+                 * corners of the tetrahedron and interpolated linearly with W.  Eq. (1) form. */
+                double Wv[4], fa[4];
+                for (int c = 0; c < 4; ++c) {
+                    Wv[c] = b[c] > 0.0 ? Wc[c] : 0.0;
+                    fa[c] = a[c];
+                }
+                btet T;
+                memset(&T, 0, sizeof T);
+                for (int v = 0; v < 4; ++v) T.b[v][v] = 1.0;
+                int n1 = clip_negative(&T, fa, S);
+                for (int s = 0; s < n1; ++s) add_piece(&S[s], Dc, Wv, +1.0, 1, nw, omega, pacc);
+                continue;
+            }
             int ns = carve_region(a, b, 1, S);
             for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, pacc);
             if (P->form == 0) {
@@ -513,22 +530,27 @@ int chi0_oracle(int n1, int n2, int n3, int nb, int no,
  * tets[n_tet][4] are corner indices into n_kp k-points; eps_k [nb][n_kp] and c_k
  * [n_kp][no][nb] hold the data at those points, eps_kq [nb][n_kp] and c_kq [n_kp][no][nb]
  * (c_kq may be NULL under CMA) the data at the same points shifted by q.  Every tetrahedron
- * is the fraction `volume` of the zone.  out: [nw][2] = (Re, Im).  Returns 0 on success.
+ * is the fraction `volume` of the zone.  single_carving = 1 (with form 1 only) replaces the
+ * second carving by the corner-interpolated final-state factor, the treatment the paper compares
+ * its method with.  out: [nw][2] = (Re, Im).  Returns 0 on success.
  */
 int chi0_oracle_list(int n_kp, int nb, int no,
                      const double *eps_k, const double *c_k,
                      const double *eps_kq, const double *c_kq,
                      long long n_tet, const int *tets, double volume,
                      double mu, double spin_factor, int band_lo, int band_hi,
-                     int cma, int form, int nw, const double *omega, int nthreads, double *out)
+                     int cma, int form, int single_carving, int nw, const double *omega, int nthreads,
+                     double *out)
 {
     if (!eps_kq || !tets || n_tet < 0 || !(volume > 0.0)) return -1;
+    if (single_carving && form != 1) return -1;
     for (long long t = 0; t < 4 * n_tet; ++t)
         if (tets[t] < 0 || tets[t] >= n_kp) return -2;
     problem P;
     int rc = setup(&P, n_kp, 1, 1, nb, no, eps_k, c_k, eps_kq, cma ? NULL : c_kq, 0, 0, 0, mu,
                    band_lo, band_hi, cma, form);
     if (rc) return rc;
+    P.single_carving = single_carving;
     int nt = 1;
 #ifdef _OPENMP
     nt = nthreads > 0 ? nthreads : omp_get_max_threads();

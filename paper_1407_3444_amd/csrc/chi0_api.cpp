@@ -147,6 +147,14 @@ struct GroupLaunch {
     bool accumulate;
 };
 
+// Tetrahedron-kernel workgroups per entry of a group call: the entries of a launch share
+// about 4096 workgroups (a group's partial sums are added together anyway, so fewer, longer
+// workgroups per entry cost nothing in balance and shorten the reduction).
+int n_blocks_group(const chi0_plan_s *p, int entries_per_launch)
+{
+    return std::max(1, std::min(n_blocks(p), 4096 / std::max(1, entries_per_launch)));
+}
+
 std::vector<GroupLaunch> group_launches(int nq, int n_group)
 {
     std::vector<GroupLaunch> out;
@@ -608,7 +616,7 @@ chi0_status chi0_static_group(chi0_plan_t p, int32_t nq, int32_t n_group, const 
     if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
     const Layout L = layout(p, ne, 1);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
-    const int nblk = n_blocks(p);
+    const int nblk = n_blocks_group(p, L.qbatch);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
     for (const GroupLaunch &G : group_launches(nq, n_group)) {
@@ -644,7 +652,7 @@ chi0_status chi0_dynamic_group(chi0_plan_t p, int32_t nq, int32_t n_group, const
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
     const Layout L = layout(p, ne, 2 * nwc_max);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
-    const int nblk = n_blocks(p);
+    const int nblk = n_blocks_group(p, L.qbatch);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
     for (const GroupLaunch &G : group_launches(nq, n_group)) {

@@ -1,6 +1,7 @@
 // k_reduce.hip -- deterministic final reduction (K_R).
 // out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], with the
-// blocks added in increasing order, so repeated runs give bitwise-identical chi0.  A sum over
+// blocks added in a fixed order (four quarters of the block range, each in increasing order),
+// so repeated runs give bitwise-identical chi0.  A sum over
 // a group of q-entries (the point-group loop) is the same sum over the group's consecutive
 // blocks, added to the earlier launches' result when a group spans several launches.
 #include "chi0_internal.h"
@@ -34,18 +35,32 @@ __global__ __launch_bounds__(256) void reduce_batch_kernel(const BatchItemDev *_
     it.out[v] = it.scale * ordered_sum(it.partial + v, it.nblocks, nvals);
 }
 
+// A workgroup takes 64 consecutive values of one q; its 4 waves sum the quarters of the block
+// range (each in block order, four running sums), and wave 0 adds the quarters in order.
 // accumulate: add to what out holds (the earlier parts of a sum split over launches) instead of
 // overwriting it.
-__global__ __launch_bounds__(256) void reduce_kernel(const double *__restrict__ partial, int nblocks, int nvals,
-                                                     double scale, double *__restrict__ out, int64_t out_stride,
-                                                     int accumulate)
+constexpr int kReduceVals = 64;
+constexpr int kReduceSlices = 4;
+
+__global__ __launch_bounds__(kReduceVals * kReduceSlices) void reduce_kernel(
+    const double *__restrict__ partial, int nblocks, int nvals, double scale, double *__restrict__ out,
+    int64_t out_stride, int accumulate)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double quarter[kReduceSlices][kReduceVals];
+    const int lane = threadIdx.x % kReduceVals, slice = threadIdx.x / kReduceVals;
+    const int v = blockIdx.x * kReduceVals + lane;
     const int q = blockIdx.y;
-    if (v >= nvals) return;
-    const double s = scale * ordered_sum(partial + (int64_t)q * nblocks * nvals + v, nblocks, nvals);
+    const int per = (nblocks + kReduceSlices - 1) / kReduceSlices;
+    const int b0 = min(nblocks, slice * per), b1 = min(nblocks, b0 + per);
+    double s = 0.0;
+    if (v < nvals && b1 > b0)
+        s = ordered_sum(partial + ((int64_t)q * nblocks + b0) * nvals + v, b1 - b0, nvals);
+    quarter[slice][lane] = s;
+    __syncthreads();
+    if (slice != 0 || v >= nvals) return;
+    const double t = scale * ((quarter[0][lane] + quarter[1][lane]) + (quarter[2][lane] + quarter[3][lane]));
     double *o = out + (int64_t)q * out_stride + v;
-    *o = accumulate ? *o + s : s;
+    *o = accumulate ? *o + t : t;
 }
 
 }  // namespace
@@ -62,7 +77,7 @@ hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, 
                          int64_t out_stride, hipStream_t s, bool accumulate)
 {
     if (nq < 1 || nblocks < 1 || nvals < 1) return hipErrorInvalidValue;
-    dim3 grid((nvals + 255) / 256, nq), block(256);
+    dim3 grid((nvals + kReduceVals - 1) / kReduceVals, nq), block(kReduceVals * kReduceSlices);
     hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, partial, nblocks, nvals, scale, out, out_stride,
                        accumulate ? 1 : 0);
     return hipGetLastError();
