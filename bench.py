@@ -324,6 +324,7 @@ def bench_iw(args):
         mqs.append(lib.Q(eps_kq=torch.from_numpy(a).to(dev), c_kq=torch.from_numpy(b).to(dev)))
     mws = mplan.workspace(len(mqs), nw)
     mout = torch.empty((len(q_list), nw, 2), dtype=torch.float64, device=dev)
+    mcensus = mplan.census(mqs, om, workspace=mws)
     mms = timed(lambda: mplan.dynamic(mqs, om, workspace=mws, out=mout), args.steps)
     mesh_val = torch.view_as_complex(mout).cpu().numpy()
     diff = float(np.max(np.abs(got - mesh_val)) / np.max(np.abs(mesh_val)))
@@ -351,7 +352,7 @@ def bench_iw(args):
               "census": census,
               "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
               "full_mesh_same_q": {"ms_per_step": mms, "value": units / (mms * 1e-3),
-                                   "max_rel_difference_vs_wedge": diff}}
+                                   "max_rel_difference_vs_wedge": diff, "census": mcensus}}
     if not args.no_cpu_baseline:
         import oracle
         threads = min(16, os.cpu_count() or 1)
