@@ -147,14 +147,6 @@ struct GroupLaunch {
     bool accumulate;
 };
 
-// Tetrahedron-kernel workgroups per entry of a group call: the entries of a launch share
-// about 4096 workgroups (a group's partial sums are added together anyway, so fewer, longer
-// workgroups per entry cost nothing in balance and shorten the reduction).
-int n_blocks_group(const chi0_plan_s *p, int entries_per_launch)
-{
-    return std::max(1, std::min(n_blocks(p), 4096 / std::max(1, entries_per_launch)));
-}
-
 std::vector<GroupLaunch> group_launches(int nq, int n_group)
 {
     std::vector<GroupLaunch> out;
@@ -411,6 +403,7 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
     const Layout L = layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch));
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     hipError_t e = hipMemsetAsync(dc, 0, 5 * sizeof(unsigned long long), p->stream);
     if (e != hipSuccess) return device_fail(p, e, "census clear");
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
@@ -419,8 +412,8 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
         fill_batch(p, qs, q0, nqb, ws, L, B);
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
-            if ((e = launch_census(p->mesh, B, nqb, omega + w0, nwc, p->d.precision != 0, w0 == 0, dc,
-                                   p->stream)) !=
+            if ((e = launch_census(p->mesh, B, nqb, n_blocks(p), omega + w0, nwc, partial, p->d.precision != 0,
+                                   w0 == 0, dc, p->stream)) !=
                 hipSuccess)
                 return device_fail(p, e, "census kernel");
         }
@@ -616,7 +609,7 @@ chi0_status chi0_static_group(chi0_plan_t p, int32_t nq, int32_t n_group, const 
     if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
     const Layout L = layout(p, ne, 1);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
-    const int nblk = n_blocks_group(p, L.qbatch);
+    const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
     for (const GroupLaunch &G : group_launches(nq, n_group)) {
@@ -652,7 +645,7 @@ chi0_status chi0_dynamic_group(chi0_plan_t p, int32_t nq, int32_t n_group, const
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
     const Layout L = layout(p, ne, 2 * nwc_max);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
-    const int nblk = n_blocks_group(p, L.qbatch);
+    const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
     for (const GroupLaunch &G : group_launches(nq, n_group)) {

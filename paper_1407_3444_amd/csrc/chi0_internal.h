@@ -101,12 +101,15 @@ hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch,
 hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
                                 const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 
-// Census of the work of a dynamic call (nw <= kMaxOmegaPerLaunch): counts[0..4] += active units,
-// final tetrahedra, near-branch and far-branch (final tetrahedron, frequency) evaluations, and
-// the far-series terms of the far evaluations (FP32 series when mixed).  Units and final
-// tetrahedra are counted only when first_chunk is set (the first frequency chunk of a call).
-hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, const double *omega, int nw,
-                         bool mixed, bool first_chunk, unsigned long long *counts, hipStream_t s);
+// Census of the work of a dynamic call (nw <= kMaxOmegaPerLaunch), by the dynamic evaluation
+// itself with counters (it also writes the call's partial sums): counts[0..4] += active units,
+// final tetrahedra, near-branch evaluations, far-branch evaluations (per final tetrahedron and
+// frequency, or per list of final tetrahedra and frequency where a list is one series), and the
+// series terms of the far evaluations (FP32 series when mixed).  Units and final tetrahedra are
+// counted only when first_chunk is set (the first frequency chunk of a call).
+hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
+                         int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,
+                         hipStream_t s);
 
 // K_R: out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], fixed order.
 hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale,

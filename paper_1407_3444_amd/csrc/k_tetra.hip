@@ -329,12 +329,20 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
     }
 }
 
+// Work counted by the census instantiation (COUNT) of the dynamic body, wave totals.
+struct WorkCount {
+    unsigned long long units, tets, near, far, terms;
+};
+
 // One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
-// partial sums for every frequency to part[nw][2].
-template <int NSLOT, bool MIXED, bool LIST>
+// partial sums for every frequency to part[nw][2].  With COUNT the same evaluation also counts
+// its work into *wc (units with a non-empty carved region and final tetrahedra only when
+// count_tets is set, so that a frequency grid split over launches counts them once).
+template <int NSLOT, bool MIXED, bool LIST, bool COUNT = false>
 __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, int nblocks, int blk,
                                              const double *__restrict__ omega, int nw, double *__restrict__ part,
-                                             DynRec *list, uint16_t (*queue)[kWave])
+                                             DynRec *list, uint16_t (*queue)[kWave], WorkCount *wc = nullptr,
+                                             bool count_tets = false)
 {
     const int lane = threadIdx.x;
     const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
@@ -370,37 +378,101 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
             load_unit<LIST>(M, Q, ux, t);
             cnt = count_unit(t, M.form);
         }
+        if (COUNT && count_tets) wc->units += __popcll(__ballot(cnt > 0));
         int start = 0;
         while (start < kWave) {
             int next;
             const int nrec = fill_list<DynRec, kCapDyn, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
+            if (COUNT && count_tets) wc->tets += nrec;
             __syncthreads();
-            // per-tetrahedron preparation, spread over the lanes
-            for (int r = lane; r < nrec; r += kWave) {
-                double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
-                double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
+            // per-tetrahedron preparation, one lane per tetrahedron (nrec <= kCapDyn < kWave)
+            const bool mine = lane < nrec;
+            double y[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+            double c0 = 0.0, hs0 = 0.0;     // centre and half-span of this lane's D values
+            if (mine) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { y[k] = list[lane].y[k]; w[k] = list[lane].w[k]; }
                 sort4(y, w);
-                const double c = 0.5 * (y[0] + y[3]), hs = 0.5 * (y[3] - y[0]);
-                const double dist = fmax(fmax(wlo - c, c - whi), 0.0);
+                c0 = 0.5 * (y[0] + y[3]);
+                hs0 = 0.5 * (y[3] - y[0]);
+            }
+            // The list as one cluster: when every frequency of the interval is far from the span
+            // [C - R, C + R] of all its D values, the weights of all its tetrahedra are one series
+            // in 1/(w - C) whose coefficients are the sums of the tetrahedra's coefficients about
+            // C (each converges at the same ratio R/|w - C| <= kRhoFar, so the truncation bound is
+            // that of a single tetrahedron), and the frequencies pay one Horner evaluation for
+            // the whole list.  Such a frequency is far from every tetrahedron of the list, so no
+            // near item arises.
+            const double clo = wave_min(mine ? c0 - hs0 : INFINITY), chi = wave_max(mine ? c0 + hs0 : -INFINITY);
+            const double C = 0.5 * (clo + chi), R = 0.5 * (chi - clo);
+            const double distC = fmax(fmax(wlo - C, C - whi), 0.0);
+            const bool cluster = R < kRhoFar * distC;
+            if (mine) {
+                const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
+                const double cc = cluster ? C : c0;
                 if (MIXED) {
                     double a[kFarTerms32];
-                    far_coeffs<kFarTerms32>(y, w, c, a);
+                    far_coeffs<kFarTerms32>(y, w, cc, a);
 #pragma unroll
-                    for (int m = 0; m < kFarTerms32; ++m) list[r].a32[m] = (float)a[m];
+                    for (int m = 0; m < kFarTerms32; ++m) list[lane].a32[m] = (float)a[m];
                 } else {
-                    far_coeffs(y, w, c, list[r].a);
+                    far_coeffs(y, w, cc, list[lane].a);
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
-                list[r].c = c;
-                list[r].hs = hs;
-                list[r].cls = far_class(hs, dist, fmax(fabs(wlo - c), fabs(whi - c)));
-                list[r].flags = (hs < kRhoFar * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
+                for (int k = 0; k < 4; ++k) { list[lane].y[k] = y[k]; list[lane].w[k] = w[k]; }
+                list[lane].c = c0;
+                list[lane].hs = hs0;
+                list[lane].cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)));
+                list[lane].flags = (hs0 < kRhoFar * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
             }
             __syncthreads();
-            for (int r = 0; r < nrec; ++r) {
+            if (cluster) {
+                // coefficients of the list about C, summed over the tetrahedra in list order into
+                // the (empty) near queue's memory, then one Horner evaluation per frequency
+                double *acl = reinterpret_cast<double *>(&queue[0][0]);
+                const int clsC = far_class(R, distC, fmax(fabs(wlo - C), fabs(whi - C)));
+                constexpr int KC = MIXED ? kFarTerms32 : kFarTerms;
+                if (lane < KC) {
+                    double sum = 0.0;
+                    for (int r = 0; r < nrec; ++r) sum += MIXED ? (double)list[r].a32[lane] : list[r].a[lane];
+                    acl[lane] = sum;
+                }
+                __syncthreads();
+                if (MIXED) {
+                    float a[kFarTerms32], tt[NSLOT], f[NSLOT];
+#pragma unroll
+                    for (int m = 0; m < kFarTerms32; ++m) a[m] = (float)acl[m];
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) tt[s] = recip32((float)(om[s] - C));
+                    horner_slots<kFarTerms32, NSLOT>(a, tt, clsC, f);
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) acc[s].re += (double)(f[s] * tt[s]);
+                    if (COUNT) {
+                        wc->far += nw;
+                        wc->terms += (unsigned long long)nw * (clsC * kFarTerms32 / kFarClasses);
+                    }
+                } else {
+                    double a[kFarTerms], tt[NSLOT], f[NSLOT];
+#pragma unroll
+                    for (int m = 0; m < kFarTerms; m += 2) {
+                        const double2 v = *reinterpret_cast<const double2 *>(&acl[m]);
+                        a[m] = v.x;
+                        a[m + 1] = v.y;
+                    }
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(om[s] - C);
+                    horner_slots<kFarTerms, NSLOT>(a, tt, clsC, f);
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) acc[s].re = fma(f[s], tt[s], acc[s].re);
+                    if (COUNT) {
+                        wc->far += nw;
+                        wc->terms += (unsigned long long)nw * (clsC * kFarTerms / kFarClasses);
+                    }
+                }
+            }
+            for (int r = 0; r < (cluster ? 0 : nrec); ++r) {
                 // far branch: all slots at once, 8 independent Horner chains on coefficients
                 // read from LDS (broadcast) into registers; the series is cut to the terms the
                 // distance between this tetrahedron and the frequency interval needs (a
@@ -416,6 +488,21 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 bool nearb[NSLOT];
 #pragma unroll
                 for (int s = 0; s < NSLOT; ++s) nearb[s] = allfar ? false : !(hs <= kRhoFar * fabs(om[s] - c));
+                if (COUNT) {
+                    unsigned long long nn = 0, nf = 0;
+#pragma unroll
+                    for (int s = 0; s < NSLOT; ++s) {
+                        nn += __popcll(__ballot(live[s] && nearb[s]));
+                        nf += __popcll(__ballot(live[s] && !nearb[s]));
+                    }
+                    if (cls == 0) {      // every frequency near: the far Horner is skipped
+                        nn += nf;
+                        nf = 0;
+                    }
+                    wc->near += nn;
+                    wc->far += nf;
+                    wc->terms += nf * (unsigned long long)(cls * (MIXED ? kFarTerms32 : kFarTerms) / kFarClasses);
+                }
                 if (cls != 0 && MIXED) {
                     float a[kFarTerms32];
 #pragma unroll
@@ -502,7 +589,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
                                                            double *__restrict__ partial)
 {
     __shared__ DynRec list[kCapDyn];
-    __shared__ uint16_t queue[kQCap][kWave];
+    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
     dynamic_body<NSLOT, MIXED, LIST>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
                                partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue);
@@ -514,7 +601,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
                                                          const int32_t *__restrict__ block_item)
 {
     __shared__ DynRec list[kCapDyn];
-    __shared__ uint16_t queue[kQCap][kWave];
+    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const BatchItemDev it = items[block_item[blockIdx.x]];
     const int blk = blockIdx.x - it.kb_begin;
     double *part = it.partial + (int64_t)blk * it.nw * 2;
@@ -707,78 +794,30 @@ __global__ __launch_bounds__(64) void tetra_static_pairs_kernel(MeshDev M, Batch
     if (threadIdx.x == 0) partial[((int64_t)qi * nblk + j) * npairs + p] = acc;
 }
 
-// Work census (diagnostic, untimed): counts, over all units of the batch, the units with
-// a non-empty carved region, the final tetrahedra, the (final tetrahedron, frequency)
-// evaluations that take the near branch and the far branch of the weight evaluation, and the
-// far-series terms those far evaluations use (the series cut to the class of the tetrahedron
-// against the launch's frequency interval, exactly as the dynamic kernel does).  At most
-// kMaxOmegaPerLaunch frequencies per launch.
-struct CensusSink {
-    const double *omega;
-    double wlo, whi;           // interval of the launch's frequencies
-    int nw;
-    int form;
-    int step;                  // series terms per class
-    unsigned long long n_tet, n_near, n_far, n_terms;
-    __device__ void one(const double D0, const double D1, const double D2, const double D3)
-    {
-        double y[4] = {D0, D1, D2, D3}, w[4] = {0.0, 0.0, 0.0, 0.0};
-        sort4(y, w);
-        const double c = 0.5 * (y[0] + y[3]), r = 0.5 * (y[3] - y[0]);
-        const int cls = far_class(r, fmax(fmax(wlo - c, c - whi), 0.0), fmax(fabs(wlo - c), fabs(whi - c)));
-        unsigned long long nn = 0;
-        for (int i = 0; i < nw; ++i) nn += (r <= kRhoFar * fabs(omega[i] - c)) ? 0ull : 1ull;
-        n_tet += 1;
-        n_near += nn;
-        n_far += (unsigned long long)nw - nn;
-        n_terms += ((unsigned long long)nw - nn) * (unsigned long long)(cls * step);
-    }
-    __device__ void operator()(const Vtx &v0, const Vtx &v1, const Vtx &v2, const Vtx &v3, double vol)
-    {
-        if (vol == 0.0) return;
-        one(v0.D, v1.D, v2.D, v3.D);
-        if (form == 1) one(-v0.D, -v1.D, -v2.D, -v3.D);
-    }
-};
-
-template <bool LIST>
-__global__ __launch_bounds__(256) void census_kernel(MeshDev M, BatchDev B, const double *__restrict__ omega, int nw,
-                                                     int step, int first_chunk,
-                                                     unsigned long long *__restrict__ counts)
+// Work census (diagnostic, untimed): the dynamic evaluation itself (8 slots, so up to
+// kMaxOmegaPerLaunch frequencies), instantiated with counters: units with a non-empty carved
+// region, final tetrahedra, (final tetrahedron, frequency) evaluations of the near branch, far
+// evaluations (one per tetrahedron and frequency on the per-tetrahedron path, one per list and
+// frequency where a whole list is evaluated as one series) and the series terms they use.
+template <bool MIXED, bool LIST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void census_kernel(
+    MeshDev M, BatchDev B, int nblocks, const double *__restrict__ omega, int nw, double *__restrict__ partial,
+    int count_tets, unsigned long long *__restrict__ counts)
 {
-    double wlo = omega[0], whi = omega[0];
-    for (int i = 1; i < nw; ++i) {
-        wlo = fmin(wlo, omega[i]);
-        whi = fmax(whi, omega[i]);
-    }
+    __shared__ DynRec list[kCapDyn];
+    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
-    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
-    CensusSink cs;
-    cs.omega = omega;
-    cs.wlo = wlo;
-    cs.whi = whi;
-    cs.nw = nw;
-    cs.form = M.form;
-    cs.step = step;
-    cs.n_tet = cs.n_near = cs.n_far = cs.n_terms = 0;
-    unsigned long long active = 0;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_units;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        Vtx t[4];
-        load_unit<LIST>(M, Q, decode_unit<LIST>(M, u), t);
-        const unsigned long long before = cs.n_tet;
-        if (!region_empty(t[0], t[1], t[2], t[3], 1)) carve_region(t[0], t[1], t[2], t[3], 1, cs);
-        if (M.form == 0 && !region_empty(t[0], t[1], t[2], t[3], 2)) carve_region(t[0], t[1], t[2], t[3], 2, cs);
-        active += cs.n_tet > before ? 1ull : 0ull;
+    WorkCount wc = {0, 0, 0, 0, 0};
+    dynamic_body<8, MIXED, LIST, true>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
+                                       partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue, &wc,
+                                       count_tets != 0);
+    if (threadIdx.x == 0) {
+        atomicAdd(&counts[0], wc.units);
+        atomicAdd(&counts[1], wc.tets);
+        atomicAdd(&counts[2], wc.near);
+        atomicAdd(&counts[3], wc.far);
+        atomicAdd(&counts[4], wc.terms);
     }
-    if (first_chunk) {
-        atomicAdd(&counts[0], active);
-        atomicAdd(&counts[1], cs.n_tet);
-    }
-    atomicAdd(&counts[2], cs.n_near);
-    atomicAdd(&counts[3], cs.n_far);
-    atomicAdd(&counts[4], cs.n_terms);
 }
 
 }  // namespace
@@ -833,18 +872,28 @@ hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_it
     return hipGetLastError();
 }
 
-hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, const double *omega, int nw,
-                         bool mixed, bool first_chunk, unsigned long long *counts, hipStream_t s)
+hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
+                         int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,
+                         hipStream_t s)
 {
-    if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch) return hipErrorInvalidValue;
-    dim3 grid(1024, nq), block(256);
-    const int step = (mixed ? kFarTerms32 : kFarTerms) / kFarClasses;
-    if (mesh.tets)
-        hipLaunchKernelGGL(census_kernel<true>, grid, block, 0, s, mesh, batch, omega, nw, step,
-                           first_chunk ? 1 : 0, counts);
-    else
-        hipLaunchKernelGGL(census_kernel<false>, grid, block, 0, s, mesh, batch, omega, nw, step,
-                           first_chunk ? 1 : 0, counts);
+    if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch || nblocks < 1) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nq), block(kWave);
+    const int ct = first_chunk ? 1 : 0;
+    if (mesh.tets) {
+        if (mixed)
+            hipLaunchKernelGGL((census_kernel<true, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial,
+                               ct, counts);
+        else
+            hipLaunchKernelGGL((census_kernel<false, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
+                               partial, ct, counts);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((census_kernel<true, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
+                               partial, ct, counts);
+        else
+            hipLaunchKernelGGL((census_kernel<false, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
+                               partial, ct, counts);
+    }
     return hipGetLastError();
 }
 

@@ -106,6 +106,60 @@ int hc_group(const double *D, const double *Wt, const double *om, int n, int fp3
     return cls;
 }
 
+// A list of nt final tetrahedra (D[nt][4], W[nt][4]) at a group of n frequencies, the way the
+// dynamic kernel evaluates a list when every frequency is far from the whole list: the span
+// [C - R, C + R] of all D values, the test R < kRhoFar * dist(C, frequency interval), each
+// tetrahedron's series about C summed in list order, the class of the list, one Horner
+// evaluation per frequency (FP64, or the FP32 form when fp32 = 1).  Returns 1 and fills
+// out[2i], out[2i+1] when the list takes that path, 0 otherwise.
+int hc_cluster(const double *D, const double *Wt, int nt, const double *om, int n, int fp32, double *out)
+{
+    double lo = om[0], hi = om[0];
+    for (int i = 1; i < n; ++i) {
+        lo = fmin(lo, om[i]);
+        hi = fmax(hi, om[i]);
+    }
+    double clo = INFINITY, chi = -INFINITY;
+    for (int r = 0; r < nt; ++r) {
+        double y[4] = {D[4 * r], D[4 * r + 1], D[4 * r + 2], D[4 * r + 3]}, w[4] = {0, 0, 0, 0};
+        sort4(y, w);
+        clo = fmin(clo, y[0]);
+        chi = fmax(chi, y[3]);
+    }
+    const double C = 0.5 * (clo + chi), R = 0.5 * (chi - clo);
+    const double distC = fmax(fmax(lo - C, C - hi), 0.0);
+    if (!(R < kRhoFar * distC)) return 0;
+    const int cls = far_class(R, distC, fmax(fabs(lo - C), fabs(hi - C)));
+    double A[kFarTerms] = {0};
+    for (int r = 0; r < nt; ++r) {
+        double y[4] = {D[4 * r], D[4 * r + 1], D[4 * r + 2], D[4 * r + 3]};
+        double w[4] = {Wt[4 * r], Wt[4 * r + 1], Wt[4 * r + 2], Wt[4 * r + 3]};
+        sort4(y, w);
+        if (fp32) {
+            double a[kFarTerms32];
+            far_coeffs<kFarTerms32>(y, w, C, a);
+            for (int m = 0; m < kFarTerms32; ++m) A[m] += (double)(float)a[m];
+        } else {
+            double a[kFarTerms];
+            far_coeffs(y, w, C, a);
+            for (int m = 0; m < kFarTerms; ++m) A[m] += a[m];
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        if (fp32) {
+            float a32[kFarTerms32];
+            for (int m = 0; m < kFarTerms32; ++m) a32[m] = (float)A[m];
+            const float t = 1.0f / (float)(om[i] - C);
+            out[2 * i] = (double)(far_horner_cls<kFarTerms32>(a32, t, cls) * t);
+        } else {
+            const double t = 1.0 / (om[i] - C);
+            out[2 * i] = far_horner_cls<kFarTerms>(A, t, cls) * t;
+        }
+        out[2 * i + 1] = 0.0;
+    }
+    return 1;
+}
+
 // The near branch alone on sorted nodes, FP64 (fp32 = 0) or the mixed form's FP32 (fp32 = 1).
 void hc_near(const double *y, const double *w, double om, int fp32, double *out)
 {

@@ -31,6 +31,8 @@ def hc():
     lib.hc_unit.restype = ctypes.c_int
     lib.hc_group.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
     lib.hc_group.restype = ctypes.c_int
+    lib.hc_cluster.argtypes = [dp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.hc_cluster.restype = ctypes.c_int
     return lib
 
 
@@ -175,3 +177,41 @@ def test_series_cut_per_frequency_group_keeps_accuracy(hc, fp32, bound):
     # the cases exercise short, intermediate and full series
     assert min(c for c in classes if c > 0) <= 2 and max(classes) == 10 and 0 in classes
     print("worst relative error", worst, "classes", np.bincount(classes))
+
+
+@pytest.mark.parametrize("fp32,bound", [(0, 5e-12), (1, 2e-6)])
+def test_list_as_one_series_matches_oracle(hc, fp32, bound):
+    """A list of final tetrahedra far from every frequency of a group, evaluated as one series about
+    the centre of its span (the sum of the tetrahedra's coefficients about that centre), matches
+    the sum of the oracle's weights; lists whose span reaches a frequency are refused."""
+    rng = np.random.default_rng(23)
+    used = refused = 0
+    worst = 0.0
+    for trial in range(120):
+        nt = int(rng.integers(1, 33))
+        c = rng.uniform(-1.0, 3.0)
+        spread = 10 ** rng.uniform(-4, -0.5)
+        D = c + rng.uniform(-spread, spread, (nt, 4))
+        if trial % 10 == 0:
+            D[:, 1] = D[:, 0]                      # tied corners
+        W = rng.uniform(-1, 1, (nt, 4))
+        om = np.sort(rng.uniform(0.0, 2.0, 64))
+        out = np.zeros(2 * len(om))
+        ok = hc.hc_cluster(_p(np.ascontiguousarray(D)), _p(np.ascontiguousarray(W)), nt, _p(om), len(om), fp32,
+                           _p(out))
+        span = (D.min(), D.max())
+        far = (0.5 * (span[1] - span[0])) < 0.4 * max(0.0, om[0] - 0.5 * sum(span), 0.5 * sum(span) - om[-1])
+        assert bool(ok) == far
+        if not ok:
+            refused += 1
+            continue
+        used += 1
+        for i in range(len(om)):
+            J = [oracle.weights(D[r], om[i]) for r in range(nt)]
+            ref = sum(np.dot(W[r], J[r]) for r in range(nt))
+            scale = sum(np.sum(np.abs(W[r]) * np.abs(J[r])) for r in range(nt))
+            err = abs(out[2 * i] - ref.real) / scale
+            worst = max(worst, err)
+            assert err < bound, (trial, nt, i, out[2 * i], ref)
+    assert used > 30 and refused > 10, (used, refused)
+    print("worst relative error", worst, "lists as one series", used, "refused", refused)
