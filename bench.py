@@ -34,10 +34,11 @@ sys.path.insert(0, ROOT)
 
 # FP64 flops per evaluation, counted from the formulas the tetrahedron kernel evaluates
 # (an FMA counts 2, a reciprocal or division 1, a logarithm 20):
-#   far  (final tetrahedron, w): d = w - c (1), |d| rho test (1), reciprocal 1/d from the
-#        hardware estimate and two Newton steps (1 + 8), accumulate (2): 11 + 2 per series term
-#        (the census counts the terms each far evaluation uses; a Horner FMA per term beyond
-#        the first, so an n-term series costs 11 + 2 n)
+#   far  (final tetrahedron, w; or a whole list of final tetrahedra, w, where the list is one
+#        series): d = w - c (1), |d| rho test (1), reciprocal 1/d from the hardware estimate and
+#        two Newton steps (1 + 8), accumulate (2): 11 + 2 per series term (the census counts the
+#        terms each far evaluation uses; a Horner FMA per term beyond the first, so an n-term
+#        series costs 11 + 2 n)
 #   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
 #        three 2-node entries (recursion 16 + 14-term series: complex low orders 61 + 11 real
 #        terms x 8 = 149, test 2: 3 x 167 + 3 = 504), two 3-node entries (recursion 16 + series:
@@ -55,8 +56,8 @@ VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "dad20e53d6983276"
-TRAFFIC_BYTES_PER_LAUNCH = (395698 * 2.0 + 340918 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA = "d1bb8a583e16f5c1"
+TRAFFIC_BYTES_PER_LAUNCH = (541048 * 2.0 + 700925 * 1.0) * 1024
 
 
 def census_flops(census: dict) -> int:
