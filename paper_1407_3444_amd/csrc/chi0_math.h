@@ -434,9 +434,11 @@ C0_HD void taylor_triple(T y1_ye, T y2_ye, T we, T w1, T w2, T u, cx<T> L, cx<T>
 // One Newton entry over nodes y[0..P] (P = 1, 2) from its two children A = [y_1..y_P] and
 // B = [y_0..y_{P-1}], or, when its nodes cluster within theta of their distance to w, from the
 // Taylor series about its end node farther from w.  y: FP64 node values; u: w - y in T.
-template <int P, class T>
+// SERIES = false (3-node entries only): the series is not evaluated; *need is set when it would
+// have been selected, and the entry then holds the (inaccurate) recursion value.
+template <int P, class T, bool SERIES = true>
 C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L, cx<T> A, cx<T> dA, cx<T> B,
-                        cx<T> dB, cx<T> &V, cx<T> &Tg)
+                        cx<T> dB, cx<T> &V, cx<T> &Tg, bool *need = nullptr)
 {
     const T span = T(y[P] - y[0]);
     const T inv = rcp(span);
@@ -448,6 +450,12 @@ C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L,
     const bool first = d0 >= dP;
     const T far = first ? d0 : dP;
     const bool use_series = span <= T(NearParams<T>::theta) * far;
+    if (!SERIES) {
+        *need = *need || use_series;
+        V = E;
+        Tg = dE;
+        return;
+    }
     const bool at_w = far == T(0);                 // every node at w: h[..] and its derivative vanish
     const T ue = at_w ? T(1) : (first ? u[0] : u[P]);
     const cx<T> Le = cxsel(first, L[0], L[P]);
@@ -471,8 +479,10 @@ C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L,
 // h is taken with Log(u) - log(s), s the span of the nodes: the dropped part log(s) u^3 is a
 // cubic, whose third divided difference is a constant, so the W-derivative is unchanged while
 // the logarithms stay O(1) (no cancellation of a large common log(s) between the leaves).
-template <class T>
-C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om)
+// TRIPLE = false: the two 3-node entries skip their series; *need reports whether either would
+// have used it (the result is then to be discarded and the full evaluation done instead).
+template <class T, bool TRIPLE = true>
+C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om, bool *need = nullptr)
 {
     T u[4], w[4];
     cx<T> L[4], V0[4], T0[4];
@@ -493,7 +503,8 @@ C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om)
     cx<T> V2[2], T2[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-        newton_entry<2, T>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i]);
+        newton_entry<2, T, TRIPLE>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i],
+                                   need);
     // the top entry spans all nodes; in the near branch its span exceeds its distance to w
     const T inv = inv_s;
     const cx<T> E = cxscale(cxsub(V2[1], V2[0]), inv);
@@ -511,6 +522,19 @@ C0_HD cplx near_eval(const double y[4], const double w[4], double om) { return n
 // Mixed form: the near branch in FP32 (see near_eval_t); the kernels keep FP64 for
 // near-degenerate tetrahedra (near_degenerate below).
 C0_HD cplx near_eval32(const double y[4], const double w[4], double om) { return near_eval_t<float>(y, w, om); }
+
+// The near branch without the series of its two 3-node entries, for callers that evaluate the
+// few items whose 3-node entries cluster (need = true) again with near_eval / near_eval32.
+C0_HD cplx near_eval_fast(const double y[4], const double w[4], double om, bool &need)
+{
+    need = false;
+    return near_eval_t<double, false>(y, w, om, &need);
+}
+C0_HD cplx near_eval32_fast(const double y[4], const double w[4], double om, bool &need)
+{
+    need = false;
+    return near_eval_t<float, false>(y, w, om, &need);
+}
 
 // ---------------------------------------------------------------------------
 // Imaginary part alone (the tetrahedron delta weights, Sec. II, Eq. (2)):

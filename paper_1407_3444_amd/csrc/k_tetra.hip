@@ -303,14 +303,31 @@ __device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T
 // lane's queue has two ends: items of the FP64 evaluation at the bottom (rows 0, 1, ...), and,
 // in the mixed form, items of the FP32 evaluation at the top (rows kQCap-1, kQCap-2, ...).
 // Lanes with an empty end idle; the loop ends when that end is empty in every lane.
-template <int NSLOT, bool F32>
+// Evaluates the lane's queued near items (tetrahedron r, slot s) and empties the queue.  With
+// TWO_PASS (the FP64 form) a first pass skips the series of the 3-node Newton entries, which few
+// items need (their nodes must cluster within theta of their distance from w) but which would
+// otherwise cost every wave that holds one such item; those items are set aside in queue
+// positions already consumed and evaluated in full by a second pass.  The FP32 near branch is
+// cheap enough that the second pass does not pay; it takes one pass.
+template <int NSLOT, bool F32, bool TWO_PASS = false>
 __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
                                            const double *__restrict__ omega, cplx *acc)
 {
+    const int top = qn;
+    int nredo = 0;
+    auto slot = [&](int p) -> uint16_t & { return queue[F32 ? kQCap - 1 - p : p][lane]; };
+    auto add = [&](int s, cplx z) {
+#pragma unroll
+        for (int ss = 0; ss < NSLOT; ++ss) {
+            const bool hit = s == ss;
+            acc[ss].re += hit ? z.re : 0.0;
+            acc[ss].im += hit ? z.im : 0.0;
+        }
+    };
     while (__any(qn > 0)) {
         if (qn > 0) {
             --qn;
-            const int e = queue[F32 ? kQCap - 1 - qn : qn][lane];
+            const int e = slot(qn);
             const int r = e >> 3, s = e & 7;
             double y[4], w[4];
 #pragma unroll
@@ -318,13 +335,28 @@ __device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)
             // the frequency is read again (a cached load) rather than picked out of the
             // lane's register array, which would be indexed dynamically
             const double o = omega[lane + kWave * s];
-            const cplx z = F32 ? near_eval32(y, w, o) : near_eval(y, w, o);
-#pragma unroll
-            for (int ss = 0; ss < NSLOT; ++ss) {
-                const bool hit = s == ss;
-                acc[ss].re += hit ? z.re : 0.0;
-                acc[ss].im += hit ? z.im : 0.0;
+            bool need = false;
+            const cplx z = !TWO_PASS ? (F32 ? near_eval32(y, w, o) : near_eval(y, w, o))
+                                     : (F32 ? near_eval32_fast(y, w, o, need) : near_eval_fast(y, w, o, need));
+            if (need) {
+                // positions top - 1 - nredo >= qn have been consumed already
+                slot(top - 1 - nredo) = (uint16_t)e;
+                ++nredo;
+            } else {
+                add(s, z);
             }
+        }
+    }
+    while (TWO_PASS && __any(nredo > 0)) {
+        if (nredo > 0) {
+            --nredo;
+            const int e = slot(top - 1 - nredo);
+            const int r = e >> 3, s = e & 7;
+            double y[4], w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
+            const double o = omega[lane + kWave * s];
+            add(s, F32 ? near_eval32(y, w, o) : near_eval(y, w, o));
         }
     }
 }
@@ -563,12 +595,12 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                         }
                     }
                     if (__any(qn + qn32 > kQCap - NSLOT)) {
-                        drain_near<NSLOT, false>(list, queue, qn, lane, omega, acc);
+                        drain_near<NSLOT, false, !MIXED>(list, queue, qn, lane, omega, acc);
                         if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
                     }
                 }
             }
-            drain_near<NSLOT, false>(list, queue, qn, lane, omega, acc);
+            drain_near<NSLOT, false, !MIXED>(list, queue, qn, lane, omega, acc);
             if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
             __syncthreads();
         }

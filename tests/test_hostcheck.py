@@ -33,6 +33,9 @@ def hc():
     lib.hc_group.restype = ctypes.c_int
     lib.hc_cluster.argtypes = [dp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
     lib.hc_cluster.restype = ctypes.c_int
+    lib.hc_near_fast.argtypes = [dp, dp, ctypes.c_double, ctypes.c_int, dp]
+    lib.hc_near_fast.restype = ctypes.c_int
+    lib.hc_near.argtypes = [dp, dp, ctypes.c_double, ctypes.c_int, dp]
     return lib
 
 
@@ -215,3 +218,29 @@ def test_list_as_one_series_matches_oracle(hc, fp32, bound):
             assert err < bound, (trial, nt, i, out[2 * i], ref)
     assert used > 30 and refused > 10, (used, refused)
     print("worst relative error", worst, "lists as one series", used, "refused", refused)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_near_first_pass_equals_full_unless_flagged(hc, fp32):
+    """The near drain's first pass (series of the 3-node entries skipped) gives bit for bit the
+    full near evaluation whenever it does not flag the item; flagged items (3-node entries whose
+    nodes cluster relative to their distance from w) are exactly those re-evaluated in full."""
+    rng = np.random.default_rng(31)
+    flagged = 0
+    for _ in range(3000):
+        y = np.sort(rng.uniform(0.0, 1.0, 4))
+        if rng.random() < 0.3:
+            k = int(rng.integers(0, 2))
+            y[k + 1] = y[k] + 10 ** rng.uniform(-8, -1) * (y[3] - y[0] + 1e-3)
+            y[k + 2] = y[k + 1] + 10 ** rng.uniform(-8, -1) * (y[3] - y[0] + 1e-3)
+            y = np.sort(y)
+        w = rng.uniform(-1, 1, 4)
+        om = rng.uniform(y[0] - 1.0, y[3] + 1.0)
+        fast, full = np.zeros(2), np.zeros(2)
+        need = hc.hc_near_fast(_p(y), _p(w), float(om), fp32, _p(fast))
+        hc.hc_near(_p(y), _p(w), float(om), fp32, _p(full))
+        if need:
+            flagged += 1
+        else:
+            assert np.array_equal(fast, full), (y, w, om, fast, full)
+    assert 30 < flagged < 2000, flagged
