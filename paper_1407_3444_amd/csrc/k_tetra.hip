@@ -31,6 +31,11 @@ namespace {
 constexpr int kCapDyn = 32;     // final tetrahedra per LDS list (dynamic)
 constexpr int kCapStat = 192;   // final tetrahedra per LDS list (static)
 constexpr int kQCap = 48;       // near-branch work items queued per lane
+// One unit yields at most 18 final tetrahedra (each region: at most 3 pieces from the first
+// carving, each cut into at most 3 by the second; form 1 stores every piece twice), and a list
+// must hold a whole unit, or filling it would never advance.
+constexpr int kMaxRecsPerUnit = 18;
+static_assert(kCapDyn >= kMaxRecsPerUnit && kCapStat >= kMaxRecsPerUnit, "a list must hold a whole unit");
 
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
@@ -711,6 +716,7 @@ struct ImRec {
     double w[4];                // sign * volume * W
 };
 constexpr int kCapIm = 64;      // final tetrahedra per LDS list
+static_assert(kCapIm >= kMaxRecsPerUnit, "a list must hold a whole unit");
 constexpr int kQCapIm = 64;     // work items queued per lane
 
 template <int NSLOT>
