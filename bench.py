@@ -56,8 +56,8 @@ VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "d1bb8a583e16f5c1"
-TRAFFIC_BYTES_PER_LAUNCH = (541048 * 2.0 + 700925 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA = "7036ae0ecec0cb25"
+TRAFFIC_BYTES_PER_LAUNCH = (544982 * 2.0 + 592905 * 1.0) * 1024
 
 
 def census_flops(census: dict) -> int:
@@ -66,10 +66,15 @@ def census_flops(census: dict) -> int:
             + census["near_evals"] * FLOPS_NEAR + census["final_tetrahedra"] * FLOPS_PREP)
 
 
-def kernel_sha() -> str:
+# The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch).
+PW_TRAFFIC_KERNEL_SHA = "a6e38c752e058dbc"
+PW_TRAFFIC_BYTES_PER_LAUNCH = (33354366 * 2.0 + 987672 * 1.0) * 1024
+
+
+def kernel_sha(files=("k_tetra.hip", "chi0_math.h")) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_tetra.hip", "chi0_math.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1407_3444_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -211,7 +216,10 @@ def bench_pw(args):
                          "mesh": list(wl.nk), "n_pw": n_pw, "n_q": len(qs), "band_pairs": nbw * nbw,
                          "units_per_step": units, "parallelism": "single GPU"},
               "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                           "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                           "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                           "traffic": (PW_TRAFFIC_BYTES_PER_LAUNCH
+                                       if len(qs) == 16 and kernel_sha(("k_contract.hip",)) == PW_TRAFFIC_KERNEL_SHA
+                                       else None),
                            "kernel": "contract_pw_kernel", "avg_launch_ms": round(avg_ms, 3),
                            "algorithmic_bytes_per_launch": bytes_launch,
                            "hbm_bound_ms": round(bytes_launch / 8e12 * 1e3, 3),
