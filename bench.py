@@ -40,14 +40,14 @@ sys.path.insert(0, ROOT)
 #        terms each far evaluation uses; a Horner FMA per term beyond the first, so an n-term
 #        series costs 11 + 2 n)
 #   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
-#        three 2-node entries (recursion 16 + 14-term series: complex low orders 61 + 11 real
-#        terms x 8 = 149, test 2: 3 x 167 + 3 = 504), two 3-node entries (recursion 16 + series:
-#        low orders 47 + 12 real terms x 16 = 239, test 2: 2 x 257 = 514), top entry 12,
+#        three 2-node entries (recursion 16 + 12-term series: complex low orders 61 + 9 real
+#        terms x 8 = 133, test 2: 3 x 151 + 3 = 456), two 3-node entries (recursion 16 + series:
+#        low orders 47 + 10 real terms x 16 = 207, test 2: 2 x 225 = 450), top entry 12,
 #        accumulate 2
 #   prep (per final tetrahedron): 40 far-series coefficients with W-derivatives (23 each) + 6
 FLOPS_FAR_BASE = 11
 FLOPS_PER_TERM = 2
-FLOPS_NEAR = 1164
+FLOPS_NEAR = 1052
 FLOPS_PREP = 926
 FP64_PEAK_TFLOPS = 78.6
 METRIC = "chi0 band-pair*tetra*omega updates/s, mixed vs FP64 GPU, at stated rel error"

@@ -322,7 +322,7 @@ C0_HD float rcp(float d)
 // kThetaEntry32 (so the Newton recursion loses at most a factor 1/kThetaEntry32 per level) and
 // needs kEntryTerms32 terms for the FP32 resolution.
 #ifndef CHI0_ENTRY_TERMS
-#define CHI0_ENTRY_TERMS 14
+#define CHI0_ENTRY_TERMS 12
 #endif
 #ifndef CHI0_ENTRY_TERMS32
 #define CHI0_ENTRY_TERMS32 10

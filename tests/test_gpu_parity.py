@@ -361,3 +361,61 @@ def test_plane_wave_dynamic_chi0():
     for i in range(len(wl.qs)):
         ref = oracle.chi0(wl, i)
         assert _relerr(got[i], ref) <= TOL
+
+
+def _host_carving_lib():
+    """The kernels' carving and weight arithmetic (chi0_math.h) compiled for the host."""
+    import ctypes
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "hostcheck", "chi0_hostcheck.cpp")
+    lib = os.path.join(here, "hostcheck", "libchi0_hostcheck_gpu.so")
+    tmp = lib + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", src, "-o", tmp])
+    os.replace(tmp, lib)
+    hc = ctypes.CDLL(lib)
+    dp = ctypes.POINTER(ctypes.c_double)
+    hc.hc_unit.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
+    hc.hc_unit.restype = ctypes.c_int
+    return hc, dp
+
+
+def test_census_counts_the_evaluation():
+    """chi0_census: the units with a non-empty carved region equal the oracle's (a count that does
+    not depend on how a carved region is cut into tetrahedra); the final tetrahedra equal those of
+    the kernels' own carving compiled for the host; every (final tetrahedron, frequency) pair is
+    evaluated near, far on its own, or far as part of a list series, so near + far evaluations
+    never exceed final tetrahedra x frequencies, and each far evaluation uses at least one term."""
+    torch = _torch()
+    hc, dp = _host_carving_lib()
+    wl = synth.make_workload("tetra_dynamic", nk=(6, 6, 2), nq=8, q_subset=[3], nw=40)
+    plan, qs = _plan(wl)
+    om = torch.from_numpy(wl.omega).cuda()
+    got = plan.census(qs, om)
+    _say("census", got)
+    q = wl.qs[0]
+    lo, hi = wl.window()
+    units = host_tets = 0
+    ones = np.ones(4)
+    out = np.zeros(2)
+    for cell in range(wl.n_k):
+        for t in range(6):
+            idx = oracle.tet_corners(wl.nk, cell, t)
+            for n in range(lo, hi):
+                for m in range(lo, hi):
+                    a = np.ascontiguousarray(wl.eps_k[n][idx] - wl.mu)
+                    b = np.ascontiguousarray(q.eps_kq[m][idx] - wl.mu)
+                    k = 0
+                    for region in (1, 2):
+                        _, vols = oracle.carve(a, b, region)
+                        k += int(np.sum(vols != 0.0))
+                    units += k > 0
+                    host_tets += hc.hc_unit(a.ctypes.data_as(dp), b.ctypes.data_as(dp), ones.ctypes.data_as(dp),
+                                            0.5, 0, out.ctypes.data_as(dp))
+    assert got["active_units"] == units
+    assert got["final_tetrahedra"] == host_tets
+    nw = len(wl.omega)
+    assert 0 < got["near_evals"] and 0 < got["far_evals"]
+    assert got["near_evals"] + got["far_evals"] <= host_tets * nw
+    assert got["far_terms"] >= got["far_evals"]
