@@ -54,7 +54,9 @@ typedef enum chi0_status {
     CHI0_OK = 0,
     CHI0_E_INVALID_ARG = -1,   /* null pointer, bad enum value, negative count */
     CHI0_E_SHAPE = -2,         /* mesh, band, orbital or window sizes out of range */
-    CHI0_E_NONFINITE = -3,     /* mu, spin factor or an omega is not finite */
+    CHI0_E_NONFINITE = -3,     /* mu, the spin factor or a spectral range is not finite (device
+                                  arrays are not scanned: a non-finite omega gives a non-finite
+                                  result at that frequency only) */
     CHI0_E_WORKSPACE = -5,     /* workspace null or smaller than chi0_workspace_size */
     CHI0_E_DEVICE = -6,        /* the HIP runtime reported an error */
     CHI0_E_UNSUPPORTED = -7    /* valid request outside what this build implements */
