@@ -419,3 +419,25 @@ def test_census_counts_the_evaluation():
     assert 0 < got["near_evals"] and 0 < got["far_evals"]
     assert got["near_evals"] + got["far_evals"] <= host_tets * nw
     assert got["far_terms"] >= got["far_evals"]
+
+
+def test_nonfinite_frequency_only_affects_itself():
+    """A NaN or infinite frequency is not rejected (device arrays are not scanned): a NaN gives NaN
+    at its own frequency and leaves every other one bit for bit unchanged; an infinite frequency
+    (whose own value is not meaningful) widens the frequency interval the series are cut for, and
+    the other frequencies keep the FP64 bar."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", nk=(6, 6, 2), nq=8, q_subset=[3], nw=40)
+    plan, qs = _plan(wl)
+    om = wl.omega.copy()
+    ref = plan.dynamic(qs, torch.from_numpy(om).cuda()).cpu().numpy()[0]
+    keep = np.ones(len(om), bool)
+    keep[7] = False
+    bad = om.copy()
+    bad[7] = np.nan
+    got = plan.dynamic(qs, torch.from_numpy(bad).cuda()).cpu().numpy()[0]
+    assert np.array_equal(got[keep], ref[keep])
+    assert np.isnan(got[7].real)
+    bad[7] = np.inf
+    got = plan.dynamic(qs, torch.from_numpy(bad).cuda()).cpu().numpy()[0]
+    assert _relerr(got[keep], ref[keep]) <= TOL
