@@ -103,7 +103,8 @@ def test_group_packing_and_accumulation():
 
 
 def test_list_of_mesh_tetrahedra_equals_mesh_plan():
-    """A list holding the mesh's own Kuhn tetrahedra gives the mesh plan's chi0 (explicit q)."""
+    """A list holding the mesh's own Kuhn tetrahedra gives the mesh plan's chi0 (explicit q), in
+    every call and in the mixed form."""
     torch = _torch()
     import paper_1407_3444_amd as lib
     nk = (6, 5, 4)
@@ -120,6 +121,24 @@ def test_list_of_mesh_tetrahedra_equals_mesh_plan():
     b = lst.dynamic(q_mesh, om).cpu().numpy()
     assert _relerr(b, a) <= 1e-13
     assert abs(lst.static(q_mesh).item() - mesh.static(q_mesh).item()) <= 1e-13 * abs(mesh.static(q_mesh).item())
+    # every other call has its list instantiation too: pair-resolved static, the Kramers-Kronig
+    # route, the census and the mixed-precision form
+    pa = mesh.static_pairs(q_mesh).cpu().numpy()
+    pb = lst.static_pairs(q_mesh).cpu().numpy()
+    assert np.max(np.abs(pb - pa)) <= 1e-13 * np.max(np.abs(pa))
+    ka = mesh.dynamic_kk(q_mesh, om, 600, -7.5, 7.5).cpu().numpy()
+    kb = lst.dynamic_kk(q_mesh, om, 600, -7.5, 7.5).cpu().numpy()
+    assert _relerr(kb, ka) <= 1e-13
+    ca, cb = mesh.census(q_mesh, om), lst.census(q_mesh, om)
+    assert ca["active_units"] == cb["active_units"] and ca["final_tetrahedra"] == cb["final_tetrahedra"]
+    assert ca["near_evals"] == cb["near_evals"]
+    mm = lib.Chi0Plan(nk, _dev(wl.eps_k), _dev(wl.c_k), mu=wl.mu, precision=1)
+    ml = lib.Chi0Plan(None, _dev(wl.eps_k), _dev(wl.c_k), mu=wl.mu, precision=1,
+                      tetrahedra=(_dev(tets), 1.0 / (6 * N)))
+    xa = mm.dynamic(q_mesh, om).cpu().numpy()
+    xb = ml.dynamic(q_mesh, om).cpu().numpy()
+    assert _relerr(xb, xa) <= 1e-12
+    assert _relerr(xb, a) <= 1e-5
     torch.cuda.synchronize()
 
 
