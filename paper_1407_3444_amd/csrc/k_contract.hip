@@ -242,7 +242,8 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
 // ---------------------------------------------------------------------------
 // Large bases (plane waves): the contraction length n_orb runs to thousands, so one k is a
 // genuine complex GEMM (nbw x n_orb)^H (n_orb x nbw) per q, and the q of one launch all share
-// the k operand.  A workgroup is one k and up to kPwQ q, one wave per q; each wave computes the
+// the k operand.  A workgroup is one k and up to kPwQ q (fewer when the launch has fewer), one wave
+// per q; each wave computes the
 // whole nbw x nbw block (NT x NT tiles of 16x16, NT = 1 or 2) over the whole reduction, so the
 // k operand is fetched from HBM once and reaches the other waves through the caches.
 //
@@ -260,6 +261,7 @@ constexpr int kPwQ = 8;      // q (waves) per workgroup
 constexpr int kXcd = 8;
 constexpr int kPwDepth = 4;  // steps of operands in flight per wave
 
+// blockDim.x / 64 q per workgroup (kPwQ, or nq when the launch has fewer).
 template <int NT>
 __global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups)
 {
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, Batch
     const int xcd = (int)(b % kXcd);
     const int64_t slot = b / kXcd;
     const int64_t k = (slot / n_qgroups) * kXcd + xcd;
-    const int qi = (int)(slot % n_qgroups) * kPwQ + wave;
+    const int qi = (int)(slot % n_qgroups) * (int)(blockDim.x >> 6) + wave;
     if (k >= M.nk || qi >= nq) return;      // no barriers below: a wave may leave on its own
     const QDev Q = B.q[qi];
     int64_t kq = k;
@@ -397,17 +399,18 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     if (mesh.no > kMaxOrbSmall) {
-        // large (plane-wave) bases: one workgroup per (k, group of kPwQ q), FP64 in every precision
+        // large (plane-wave) bases: one workgroup per (k, group of up to kPwQ q), FP64 in every precision
         if (mesh.nbw > 32) return hipErrorInvalidValue;
-        const int ng = (nq + kPwQ - 1) / kPwQ;
+        const int gq = nq < kPwQ ? nq : kPwQ;           // q (waves) per workgroup
+        const int ng = (nq + gq - 1) / gq;
         const int64_t k_per_xcd = (mesh.nk + kXcd - 1) / kXcd;
         const int64_t nblk = k_per_xcd * kXcd * ng;
         if (nblk >= (int64_t(1) << 31)) return hipErrorInvalidValue;
         if (mesh.nbw > 16)
-            hipLaunchKernelGGL(contract_pw_kernel<2>, dim3((unsigned)nblk), dim3(64 * kPwQ), 0, s, mesh, batch,
+            hipLaunchKernelGGL(contract_pw_kernel<2>, dim3((unsigned)nblk), dim3(64 * gq), 0, s, mesh, batch,
                                nq, ng);
         else
-            hipLaunchKernelGGL(contract_pw_kernel<1>, dim3((unsigned)nblk), dim3(64 * kPwQ), 0, s, mesh, batch,
+            hipLaunchKernelGGL(contract_pw_kernel<1>, dim3((unsigned)nblk), dim3(64 * gq), 0, s, mesh, batch,
                                nq, ng);
         return hipGetLastError();
     }
