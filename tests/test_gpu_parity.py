@@ -441,3 +441,28 @@ def test_nonfinite_frequency_only_affects_itself():
     bad[7] = np.inf
     got = plan.dynamic(qs, torch.from_numpy(bad).cuda()).cpu().numpy()[0]
     assert _relerr(got[keep], ref[keep]) <= TOL
+
+
+def test_frequencies_on_corner_values_and_widest_window():
+    """Frequencies equal to corner values e' - e of the mesh (a node of the divided differences at
+    w exactly), and the widest band window (32 bands of a 32-orbital model: 2x2 tiles of the
+    matrix elements, 1024 band pairs), against the oracle."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", nk=(6, 6, 2), nq=8, q_subset=[3], nw=8)
+    q = wl.qs[0]
+    rng = np.random.default_rng(5)
+    D = (q.eps_kq[:, None, :] - wl.eps_k[None, :, :]).ravel()
+    on = np.sort(rng.choice(D[(D > 0.05) & (D < 2.0)], 12, replace=False))
+    wl.omega = np.concatenate([on, [0.0]])
+    plan, qs = _plan(wl)
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()[0]
+    ref = oracle.chi0(wl, 0)
+    assert np.all(np.isfinite(got))
+    assert _relerr(got, ref) <= TOL
+    m = synth.random_model("tetragonal", 77, 32)
+    wl = synth.model_workload(m, (4, 4, 3), [np.array([0.13, 0.07, 0.21])], synth.omega_grid(24))
+    assert wl.window() == (0, 32)
+    plan, qs = _plan(wl)
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()[0]
+    ref = oracle.chi0(wl, 0)
+    assert _relerr(got, ref) <= TOL
