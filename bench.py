@@ -67,8 +67,8 @@ def census_flops(census: dict) -> int:
 
 
 # The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch).
-PW_TRAFFIC_KERNEL_SHA = "a6e38c752e058dbc"
-PW_TRAFFIC_BYTES_PER_LAUNCH = (33354366 * 2.0 + 987672 * 1.0) * 1024
+PW_TRAFFIC_KERNEL_SHA = "a205e9b07bc4afcf"
+PW_TRAFFIC_BYTES_PER_LAUNCH = (33201068 * 2.0 + 989042 * 1.0) * 1024
 
 
 def kernel_sha(files=("k_tetra.hip", "chi0_math.h")) -> str:
