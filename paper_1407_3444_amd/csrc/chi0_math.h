@@ -39,8 +39,8 @@ namespace chi0 {
 
 constexpr double kPi = 3.14159265358979323846;
 #ifndef CHI0_FAR_TERMS
-#define CHI0_FAR_TERMS 40
-#define CHI0_RHO_FAR 0.4
+#define CHI0_FAR_TERMS 50
+#define CHI0_RHO_FAR 0.5
 #endif
 #ifndef CHI0_THETA_ENTRY
 #define CHI0_THETA_ENTRY 0.1
@@ -48,9 +48,15 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kFarTerms = CHI0_FAR_TERMS;          // series terms kept in the far branch
 constexpr double kRhoFar = CHI0_RHO_FAR;           // far branch when half-span <= kRhoFar * |w - c|
 constexpr double kThetaEntry = CHI0_THETA_ENTRY;   // series sub-entry when span <= kThetaEntry * |w - x_end|
-// Mixed-precision form: the far series in FP32 with kFarTerms32 terms (0.4^20 ~ 1e-8, the
-// FP32 resolution); near and clustered tetrahedra keep the FP64 evaluation.
-constexpr int kFarTerms32 = 20;
+// Mixed-precision form: the far series in FP32 with kFarTerms32 terms at the ratio kRhoFar32
+// (0.4^20 ~ 1e-8, the FP32 resolution); its near branch runs in FP32 and is cheap enough that
+// the smaller ratio pays.  Near-degenerate tetrahedra keep the FP64 near evaluation.
+#ifndef CHI0_FAR_TERMS32
+#define CHI0_FAR_TERMS32 20
+#define CHI0_RHO_FAR32 0.4
+#endif
+constexpr int kFarTerms32 = CHI0_FAR_TERMS32;
+constexpr double kRhoFar32 = CHI0_RHO_FAR32;
 
 struct cplx {
     double re, im;
@@ -235,11 +241,12 @@ C0_HD void far_coeffs(const double y[4], const double w[4], double c, double *a)
     }
 }
 
+template <int K = kFarTerms>
 C0_HD double far_horner(const double *a, double t)
 {
-    double s = a[kFarTerms - 1];
+    double s = a[K - 1];
 #pragma unroll
-    for (int m = kFarTerms - 2; m >= 0; --m) s = fma(s, t, a[m]);
+    for (int m = K - 2; m >= 0; --m) s = fma(s, t, a[m]);
     return s * t;
 }
 
@@ -254,14 +261,15 @@ C0_HD double far_horner(const double *a, double t)
 // j >= kFarClasses ln(kRhoFar) / ln(rho_g); class 0 when every frequency of the group is near.
 constexpr int kFarClasses = 10;
 
-C0_HD int far_class(double hs, double dist, double dfar)
+// (rho is the far ratio of the form: kRhoFar, or kRhoFar32 for the FP32 series.)
+C0_HD int far_class(double hs, double dist, double dfar, double rho = kRhoFar)
 {
-    if (!(hs <= kRhoFar * dfar)) return 0;              // the farthest frequency is near too
-    if (!(hs < kRhoFar * dist)) return kFarClasses;     // rho_g = kRhoFar (also dist = 0)
-    // j = ceil(kFarClasses log2(1/kRhoFar) / log2(dist/hs)) with a small upward margin; a huge
+    if (!(hs <= rho * dfar)) return 0;              // the farthest frequency is near too
+    if (!(hs < rho * dist)) return kFarClasses;     // rho_g = rho (also dist = 0)
+    // j = ceil(kFarClasses log2(1/rho) / log2(dist/hs)) with a small upward margin; a huge
     // ratio (hs = 0 included) gives log2 = inf and class 1
     const float lx = log2f((float)(dist / hs));
-    const float q = (float)kFarClasses * log2f((float)(1.0 / kRhoFar)) * 1.00001f / lx;
+    const float q = (float)kFarClasses * log2f((float)(1.0 / rho)) * 1.00001f / lx;
     const int j = (int)ceilf(q);
     return j < 1 ? 1 : (j > kFarClasses ? kFarClasses : j);
 }
@@ -609,17 +617,23 @@ C0_HD bool near_degenerate(const double y[4], double tol)
     return !(y[1] - y[0] >= tol && y[2] - y[1] >= tol && y[3] - y[2] >= tol);
 }
 
-// sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.
+// sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.  With a single
+// frequency the coefficient recurrence is not shared, so a far evaluation costs about as much per
+// term as the recurrence; the far branch is taken at the smaller ratio kRhoOne with kTermsOne
+// terms (kRhoOne^kTermsOne ~ 1e-16), where the near branch is cheaper than a longer series.
+constexpr double kRhoOne = 0.4;
+constexpr int kTermsOne = 40;
+
 C0_HD cplx tetra_weight_sum(const double D[4], const double Wt[4], double om)
 {
     double y[4] = {D[0], D[1], D[2], D[3]}, w[4] = {Wt[0], Wt[1], Wt[2], Wt[3]};
     sort4(y, w);
     const double c = 0.5 * (y[0] + y[3]), r = 0.5 * (y[3] - y[0]);
     const double d = om - c;
-    if (r <= kRhoFar * fabs(d)) {
-        double a[kFarTerms];
-        far_coeffs(y, w, c, a);
-        return cmk(far_horner(a, 1.0 / d), 0.0);
+    if (r <= kRhoOne * fabs(d)) {
+        double a[kTermsOne];
+        far_coeffs<kTermsOne>(y, w, c, a);
+        return cmk(far_horner<kTermsOne>(a, 1.0 / d), 0.0);
     }
     return near_eval(y, w, om);
 }

@@ -30,13 +30,19 @@ namespace {
 
 constexpr int kCapDyn = 32;     // final tetrahedra per LDS list (dynamic)
 constexpr int kCapStat = 192;   // final tetrahedra per LDS list (static)
-constexpr int kQCap = 48;       // near-branch work items queued per lane
+// Near-branch work items queued per lane.  36 rows keep the FP64 form's list and queue within
+// 20 KiB, so that eight one-wave workgroups (two per SIMD, the register limit) fit in the 160 KiB
+// of LDS of a CU.
+constexpr int kQCap = 36;
 // One unit yields at most 18 final tetrahedra (each region: at most 3 pieces from the first
 // carving, each cut into at most 3 by the second; form 1 stores every piece twice), and a list
 // must hold a whole unit, or filling it would never advance.
 constexpr int kMaxRecsPerUnit = 18;
 static_assert(kCapDyn >= kMaxRecsPerUnit && kCapStat >= kMaxRecsPerUnit, "a list must hold a whole unit");
 
+// A final tetrahedron of a dynamic list.  The series storage is sized for the form, so the mixed
+// form's shorter FP32 series keeps its lists small in LDS.
+template <bool MIXED>
 struct DynRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W at the same corners
@@ -45,10 +51,16 @@ struct DynRec {
     int32_t flags;              // prep pass: 1 = no frequency of the interval is near,
                                 // 2 = near-degenerate (kept FP64 in the mixed form)
     union {
-        alignas(16) double a[kFarTerms];     // far-branch series coefficients (FP64 form)
-        alignas(16) float a32[kFarTerms32];  // the same series, first kFarTerms32 terms (mixed form)
+        alignas(16) double a[MIXED ? kFarTerms32 / 2 : kFarTerms];      // series coefficients (FP64 form)
+        alignas(16) float a32[MIXED ? kFarTerms32 : 2 * kFarTerms];     // the FP32 series (mixed form)
     };
 };
+
+static_assert(kCapDyn * sizeof(DynRec<false>) + kQCap * kWave * sizeof(uint16_t) <= 160 * 1024 / 8,
+              "eight FP64 dynamic workgroups fit the LDS of a CU");
+static_assert(kQCap * kWave * sizeof(uint16_t) >= kFarTerms * sizeof(double),
+              "a list's summed series fits the near queue's memory");
+static_assert(kFarTerms32 % 4 == 0 && kFarTerms32 <= 2 * kFarTerms, "FP32 series read four at a time, inside the union");
 
 struct StatRec {
     double D[4];
@@ -304,6 +316,34 @@ __device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T
     }
 }
 
+// The same FP64 sums with the coefficients read from LDS (broadcast reads) one block of terms at
+// a time, the next block fetched while the current one is summed, so that only two blocks are
+// held in registers rather than the whole series.  The block loop runs cls times (wave-uniform).
+template <int K, int NSLOT>
+__device__ __forceinline__ void horner_slots_lds(const double *a, const double *tt, int cls, double *f)
+{
+    constexpr int S = K / kFarClasses;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) f[s] = 0.0;
+    if (cls <= 0) return;
+    double b[S];
+#pragma unroll
+    for (int m = 0; m < S; ++m) b[m] = a[(cls - 1) * S + m];
+    for (int j = cls; j >= 1; --j) {
+        double nb[S];
+        const int nj = j > 1 ? j - 2 : 0;     // next block (clamped: always inside the series)
+#pragma unroll
+        for (int m = 0; m < S; ++m) nb[m] = a[nj * S + m];
+#pragma unroll
+        for (int m = S - 1; m >= 0; --m) {
+#pragma unroll
+            for (int s = 0; s < NSLOT; ++s) f[s] = fma(f[s], tt[s], b[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < S; ++m) b[m] = nb[m];
+    }
+}
+
 // Evaluate this lane's queued near-branch items (tetrahedron r, slot s), newest first.  Each
 // lane's queue has two ends: items of the FP64 evaluation at the bottom (rows 0, 1, ...), and,
 // in the mixed form, items of the FP32 evaluation at the top (rows kQCap-1, kQCap-2, ...).
@@ -314,8 +354,8 @@ __device__ __forceinline__ void horner_slots(const T *a, const T *tt, int cls, T
 // otherwise cost every wave that holds one such item; those items are set aside in queue
 // positions already consumed and evaluated in full by a second pass.  The FP32 near branch is
 // cheap enough that the second pass does not pay; it takes one pass.
-template <int NSLOT, bool F32, bool TWO_PASS = false>
-__device__ __forceinline__ void drain_near(const DynRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
+template <int NSLOT, bool F32, bool TWO_PASS = false, class Rec>
+__device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kWave], int &qn, int lane,
                                            const double *__restrict__ omega, cplx *acc)
 {
     const int top = qn;
@@ -378,11 +418,12 @@ struct WorkCount {
 template <int NSLOT, bool MIXED, bool LIST, bool COUNT = false>
 __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, int nblocks, int blk,
                                              const double *__restrict__ omega, int nw, double *__restrict__ part,
-                                             DynRec *list, uint16_t (*queue)[kWave], WorkCount *wc = nullptr,
+                                             DynRec<MIXED> *list, uint16_t (*queue)[kWave], WorkCount *wc = nullptr,
                                              bool count_tets = false)
 {
     const int lane = threadIdx.x;
     const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
+    constexpr double kRho = MIXED ? kRhoFar32 : kRhoFar;     // far ratio of the series in use
 
     // frequencies of this lane (slot s holds w[lane + 64 s]; dead lanes repeat the last one)
     // and their interval [wlo, whi] over the wave, from which each tetrahedron's far-series
@@ -419,7 +460,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
         int start = 0;
         while (start < kWave) {
             int next;
-            const int nrec = fill_list<DynRec, kCapDyn, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
+            const int nrec = fill_list<DynRec<MIXED>, kCapDyn, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
             start = next;
             if (nrec == 0) continue;
             if (COUNT && count_tets) wc->tets += nrec;
@@ -438,18 +479,18 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
             // The list as one cluster: when every frequency of the interval is far from the span
             // [C - R, C + R] of all its D values, the weights of all its tetrahedra are one series
             // in 1/(w - C) whose coefficients are the sums of the tetrahedra's coefficients about
-            // C (each converges at the same ratio R/|w - C| <= kRhoFar, so the truncation bound is
+            // C (each converges at the same ratio R/|w - C| <= kRho, so the truncation bound is
             // that of a single tetrahedron), and the frequencies pay one Horner evaluation for
             // the whole list.  Such a frequency is far from every tetrahedron of the list, so no
             // near item arises.
             const double clo = wave_min(mine ? c0 - hs0 : INFINITY), chi = wave_max(mine ? c0 + hs0 : -INFINITY);
             const double C = 0.5 * (clo + chi), R = 0.5 * (chi - clo);
             const double distC = fmax(fmax(wlo - C, C - whi), 0.0);
-            const bool cluster = R < kRhoFar * distC;
+            const bool cluster = R < kRho * distC;
             if (mine) {
                 const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
                 const double cc = cluster ? C : c0;
-                if (MIXED) {
+                if constexpr (MIXED) {
                     double a[kFarTerms32];
                     far_coeffs<kFarTerms32>(y, w, cc, a);
 #pragma unroll
@@ -461,19 +502,22 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 for (int k = 0; k < 4; ++k) { list[lane].y[k] = y[k]; list[lane].w[k] = w[k]; }
                 list[lane].c = c0;
                 list[lane].hs = hs0;
-                list[lane].cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)));
-                list[lane].flags = (hs0 < kRhoFar * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
+                list[lane].cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
+                list[lane].flags = (hs0 < kRho * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
             }
             __syncthreads();
             if (cluster) {
                 // coefficients of the list about C, summed over the tetrahedra in list order into
                 // the (empty) near queue's memory, then one Horner evaluation per frequency
                 double *acl = reinterpret_cast<double *>(&queue[0][0]);
-                const int clsC = far_class(R, distC, fmax(fabs(wlo - C), fabs(whi - C)));
+                const int clsC = far_class(R, distC, fmax(fabs(wlo - C), fabs(whi - C)), kRho);
                 constexpr int KC = MIXED ? kFarTerms32 : kFarTerms;
                 if (lane < KC) {
                     double sum = 0.0;
-                    for (int r = 0; r < nrec; ++r) sum += MIXED ? (double)list[r].a32[lane] : list[r].a[lane];
+                    for (int r = 0; r < nrec; ++r) {
+                        if constexpr (MIXED) sum += (double)list[r].a32[lane];
+                        else sum += list[r].a[lane];
+                    }
                     acl[lane] = sum;
                 }
                 __syncthreads();
@@ -491,16 +535,10 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                         wc->terms += (unsigned long long)nw * (clsC * kFarTerms32 / kFarClasses);
                     }
                 } else {
-                    double a[kFarTerms], tt[NSLOT], f[NSLOT];
-#pragma unroll
-                    for (int m = 0; m < kFarTerms; m += 2) {
-                        const double2 v = *reinterpret_cast<const double2 *>(&acl[m]);
-                        a[m] = v.x;
-                        a[m + 1] = v.y;
-                    }
+                    double tt[NSLOT], f[NSLOT];
 #pragma unroll
                     for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(om[s] - C);
-                    horner_slots<kFarTerms, NSLOT>(a, tt, clsC, f);
+                    horner_slots_lds<kFarTerms, NSLOT>(acl, tt, clsC, f);
 #pragma unroll
                     for (int s = 0; s < NSLOT; ++s) acc[s].re = fma(f[s], tt[s], acc[s].re);
                     if (COUNT) {
@@ -524,7 +562,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 const bool f32 = MIXED && (flags & 2) == 0;
                 bool nearb[NSLOT];
 #pragma unroll
-                for (int s = 0; s < NSLOT; ++s) nearb[s] = allfar ? false : !(hs <= kRhoFar * fabs(om[s] - c));
+                for (int s = 0; s < NSLOT; ++s) nearb[s] = allfar ? false : !(hs <= kRho * fabs(om[s] - c));
                 if (COUNT) {
                     unsigned long long nn = 0, nf = 0;
 #pragma unroll
@@ -562,25 +600,19 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                         for (int s = 0; s < NSLOT; ++s)
                             if (!nearb[s]) acc[s].re += (double)(f[s] * tt[s]);
                     }
-                } else if (cls != 0) {
-                    double a[kFarTerms];
-#pragma unroll
-                    for (int m = 0; m < kFarTerms; m += 2) {
-                        const double2 v = *reinterpret_cast<const double2 *>(&list[r].a[m]);
-                        a[m] = v.x;
-                        a[m + 1] = v.y;
-                    }
+                } else if (!MIXED && cls != 0) {
+                    const double *a = list[r].a;
                     double tt[NSLOT], f[NSLOT];
                     if (allfar) {
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(om[s] - c);
-                        horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
+                        horner_slots_lds<kFarTerms, NSLOT>(a, tt, cls, f);
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s) acc[s].re = fma(f[s], tt[s], acc[s].re);
                     } else {
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s) tt[s] = rcp(nearb[s] ? 1.0 : om[s] - c);
-                        horner_slots<kFarTerms, NSLOT>(a, tt, cls, f);
+                        horner_slots_lds<kFarTerms, NSLOT>(a, tt, cls, f);
 #pragma unroll
                         for (int s = 0; s < NSLOT; ++s)
                             if (!nearb[s]) acc[s].re = fma(f[s], tt[s], acc[s].re);
@@ -625,7 +657,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
                                                            const double *__restrict__ omega, int nw,
                                                            double *__restrict__ partial)
 {
-    __shared__ DynRec list[kCapDyn];
+    __shared__ DynRec<MIXED> list[kCapDyn];
     __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
     dynamic_body<NSLOT, MIXED, LIST>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
@@ -637,8 +669,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_batch_kernel(const BatchItemDev *__restrict__ items,
                                                          const int32_t *__restrict__ block_item)
 {
-    __shared__ DynRec list[kCapDyn];
+    // one list buffer for both forms, sized for the larger FP64 record
+    __shared__ __attribute__((aligned(16))) unsigned char lbuf[kCapDyn * sizeof(DynRec<false>)];
     __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
+    static_assert(sizeof(DynRec<true>) <= sizeof(DynRec<false>), "mixed records fit the FP64 buffer");
+    DynRec<false> *list = reinterpret_cast<DynRec<false> *>(lbuf);
+    DynRec<true> *list32 = reinterpret_cast<DynRec<true> *>(lbuf);
     const BatchItemDev it = items[block_item[blockIdx.x]];
     const int blk = blockIdx.x - it.kb_begin;
     double *part = it.partial + (int64_t)blk * it.nw * 2;
@@ -649,7 +685,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
         dynamic_body<S, false, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);          \
         break;                                                                                            \
     case 2 * S + 1:                                                                                       \
-        dynamic_body<S, true, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);           \
+        dynamic_body<S, true, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list32, queue);         \
         break;
         C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
 #undef C0_CASE
@@ -842,7 +878,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
     MeshDev M, BatchDev B, int nblocks, const double *__restrict__ omega, int nw, double *__restrict__ partial,
     int count_tets, unsigned long long *__restrict__ counts)
 {
-    __shared__ DynRec list[kCapDyn];
+    __shared__ DynRec<MIXED> list[kCapDyn];
     __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
     WorkCount wc = {0, 0, 0, 0, 0};

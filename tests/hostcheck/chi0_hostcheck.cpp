@@ -29,6 +29,10 @@ struct Acc {
 
 extern "C" {
 
+// far-branch ratio of the multi-frequency kernels (half-span over distance from the centre), of
+// the FP64 series or (fp32 = 1) of the FP32 series of the mixed form
+double hc_rho_far(int fp32) { return fp32 ? kRhoFar32 : kRhoFar; }
+
 // sum_j W_j J_j(w; D) for one final tetrahedron; out = (re, im)
 void hc_weight_sum(const double *D, const double *W, double om, double *out)
 {
@@ -79,7 +83,8 @@ int hc_group(const double *D, const double *Wt, const double *om, int n, int fp3
         lo = fmin(lo, om[i]);
         hi = fmax(hi, om[i]);
     }
-    const int cls = far_class(hs, fmax(fmax(lo - c, c - hi), 0.0), fmax(fabs(lo - c), fabs(hi - c)));
+    const double rho = fp32 ? kRhoFar32 : kRhoFar;
+    const int cls = far_class(hs, fmax(fmax(lo - c, c - hi), 0.0), fmax(fabs(lo - c), fabs(hi - c)), rho);
     double a[kFarTerms];
     far_coeffs(y, w, c, a);
     double a32d[kFarTerms32];
@@ -88,7 +93,7 @@ int hc_group(const double *D, const double *Wt, const double *om, int n, int fp3
     for (int m = 0; m < kFarTerms32; ++m) a32[m] = (float)a32d[m];
     for (int i = 0; i < n; ++i) {
         const double d = om[i] - c;
-        const bool nearb = !(hs <= kRhoFar * fabs(d));
+        const bool nearb = !(hs <= rho * fabs(d));
         far_out[i] = nearb ? 0 : 1;
         cplx z;
         if (nearb) {
@@ -108,7 +113,7 @@ int hc_group(const double *D, const double *Wt, const double *om, int n, int fp3
 
 // A list of nt final tetrahedra (D[nt][4], W[nt][4]) at a group of n frequencies, the way the
 // dynamic kernel evaluates a list when every frequency is far from the whole list: the span
-// [C - R, C + R] of all D values, the test R < kRhoFar * dist(C, frequency interval), each
+// [C - R, C + R] of all D values, the test R < rho * dist(C, frequency interval), each
 // tetrahedron's series about C summed in list order, the class of the list, one Horner
 // evaluation per frequency (FP64, or the FP32 form when fp32 = 1).  Returns 1 and fills
 // out[2i], out[2i+1] when the list takes that path, 0 otherwise.
@@ -128,8 +133,9 @@ int hc_cluster(const double *D, const double *Wt, int nt, const double *om, int 
     }
     const double C = 0.5 * (clo + chi), R = 0.5 * (chi - clo);
     const double distC = fmax(fmax(lo - C, C - hi), 0.0);
-    if (!(R < kRhoFar * distC)) return 0;
-    const int cls = far_class(R, distC, fmax(fabs(lo - C), fabs(hi - C)));
+    const double rho = fp32 ? kRhoFar32 : kRhoFar;
+    if (!(R < rho * distC)) return 0;
+    const int cls = far_class(R, distC, fmax(fabs(lo - C), fabs(hi - C)), rho);
     double A[kFarTerms] = {0};
     for (int r = 0; r < nt; ++r) {
         double y[4] = {D[4 * r], D[4 * r + 1], D[4 * r + 2], D[4 * r + 3]};

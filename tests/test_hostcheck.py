@@ -27,6 +27,8 @@ def hc():
     lib = ctypes.CDLL(LIB)
     dp = ctypes.POINTER(ctypes.c_double)
     lib.hc_weight_sum.argtypes = [dp, dp, ctypes.c_double, dp]
+    lib.hc_rho_far.argtypes = [ctypes.c_int]
+    lib.hc_rho_far.restype = ctypes.c_double
     lib.hc_unit.argtypes = [dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
     lib.hc_unit.restype = ctypes.c_int
     lib.hc_group.argtypes = [dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
@@ -203,7 +205,7 @@ def test_list_as_one_series_matches_oracle(hc, fp32, bound):
         ok = hc.hc_cluster(_p(np.ascontiguousarray(D)), _p(np.ascontiguousarray(W)), nt, _p(om), len(om), fp32,
                            _p(out))
         span = (D.min(), D.max())
-        far = (0.5 * (span[1] - span[0])) < 0.4 * max(0.0, om[0] - 0.5 * sum(span), 0.5 * sum(span) - om[-1])
+        far = (0.5 * (span[1] - span[0])) < hc.hc_rho_far(fp32) * max(0.0, om[0] - 0.5 * sum(span), 0.5 * sum(span) - om[-1])
         assert bool(ok) == far
         if not ok:
             refused += 1
