@@ -13,7 +13,9 @@
 // is therefore the directional derivative of G along (W_1..W_4), evaluated
 // here by forward-mode differentiation of the divided-difference computation.
 //
-//  * far branch (all nodes within kRhoFar * |w - c| of their centre c):
+//  * far branch (all nodes within rho * |w - c| of their centre c; rho = kRhoFar for the FP64
+//    series of the multi-frequency kernels, kRhoFar32 for their FP32 series, kRhoOne for a
+//    single frequency):
 //    G = sum_m h^(3+m)(c)/(3+m)! H_m(D - c), H_m the complete homogeneous
 //    symmetric polynomial.  Its W-derivative is a power series in
 //    t = 1/(w - c) whose coefficients depend only on the tetrahedron, so they
@@ -252,13 +254,13 @@ C0_HD double far_horner(const double *a, double t)
 
 // Truncation of the far series for a group of frequencies (all frequencies one wave evaluates
 // together, i.e. those of one launch).  A frequency of the group that takes the far branch has
-// |w - c| >= max(dist, hs / kRhoFar), dist = distance from c to the group's frequency interval,
-// so its ratio hs / |w - c| is at most rho_g = min(kRhoFar, hs / dist).  The remainder after n
-// terms is bounded by a factor polynomial in n times rho_g^n |t|, so n <= K terms with
-// rho_g^n <= kRhoFar^K keep the error bound of the full K-term series at the largest ratio
-// kRhoFar.  The group gets class
+// |w - c| >= max(dist, hs / rho), dist = distance from c to the group's frequency interval and
+// rho the form's far ratio, so its ratio hs / |w - c| is at most rho_g = min(rho, hs / dist).  The
+// remainder after n terms is bounded by a factor polynomial in n times rho_g^n |t|, so n <= K terms
+// with rho_g^n <= rho^K keep the error bound of the full K-term series at the largest ratio rho.
+// The group gets class
 // j = 1..kFarClasses (n = j K / kFarClasses terms), the smallest j with
-// j >= kFarClasses ln(kRhoFar) / ln(rho_g); class 0 when every frequency of the group is near.
+// j >= kFarClasses ln(rho) / ln(rho_g); class 0 when every frequency of the group is near.
 constexpr int kFarClasses = 10;
 
 // (rho is the far ratio of the form: kRhoFar, or kRhoFar32 for the FP32 series.)
