@@ -56,7 +56,7 @@ VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "728288aed268a02c"
+TRAFFIC_KERNEL_SHA = "0eb40fa6ade9307d"
 TRAFFIC_BYTES_PER_LAUNCH = (529870 * 2.0 + 476736 * 1.0) * 1024
 
 
