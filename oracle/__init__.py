@@ -54,6 +54,10 @@ def _load():
         lib.chi0_oracle_list.argtypes = [i, i, i, dp, dp, dp, dp, ll, ctypes.POINTER(ctypes.c_int), d, d, d, i, i,
                                          i, i, i, i, dp, i, dp]
         lib.chi0_oracle_list.restype = i
+        lib.chi0_oracle_z.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, dp, d, i, dp]
+        lib.chi0_oracle_z.restype = i
+        lib.chi0_oracle_W.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, i, i, dp]
+        lib.chi0_oracle_W.restype = i
         lib.chi0_oracle_tet_corners.argtypes = [i, i, i, ll, i, ctypes.POINTER(ctypes.c_longlong)]
         lib.chi0_oracle_tet_corners.restype = None
         _lib = lib
@@ -97,6 +101,25 @@ def chi0_raw(nk, eps_k, c_k, omega, *, eps_kq=None, c_kq=None, shift=(0, 0, 0), 
                          omega.size, _ptr(omega), c0, c1, int(nthreads), _ptr(out))
     if rc != 0:
         raise ValueError("chi0_oracle failed with code %d" % rc)
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def chi0_z_raw(nk, eps_k, c_k, omega, eta: float, *, eps_kq=None, c_kq=None, shift=(0, 0, 0), mu=0.0,
+               spin_factor=2.0, band_lo=0, band_hi=-1, cma=False, nthreads: int = 0) -> np.ndarray:
+    """The same tetrahedron integral (difference form) at complex frequencies z = omega + i eta,
+    eta >= 0: complex array [nw].  eta = 0 is chi0_raw's retarded result."""
+    lib = _load()
+    eps_k = _f64(eps_k)
+    nb = eps_k.shape[0]
+    no = 1 if c_k is None else c_k.shape[1]
+    omega = _f64(np.atleast_1d(omega))
+    out = np.zeros((omega.size, 2))
+    rc = lib.chi0_oracle_z(int(nk[0]), int(nk[1]), int(nk[2]), nb, no, _ptr(eps_k), _ptr(_c128_as_f64(c_k)),
+                           _ptr(_f64(eps_kq)), _ptr(_c128_as_f64(c_kq)), int(shift[0]), int(shift[1]),
+                           int(shift[2]), float(mu), float(spin_factor), int(band_lo), int(band_hi),
+                           int(bool(cma)), omega.size, _ptr(omega), float(eta), int(nthreads), _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle_z failed with code %d" % rc)
     return out[:, 0] + 1j * out[:, 1]
 
 
@@ -250,6 +273,32 @@ def chi0_kk(wl, q_index: int, omega, n_spec: int, lo: float, hi: float, nthreads
     im_direct = chi0(wl, q_index, omega=om, nthreads=nthreads).imag
     re = kk_tent_matrix(om, lo, hi, n_spec) @ im_grid / np.pi
     return re + 1j * im_direct
+
+
+def matrix_elements_raw(nk, c_k, *, c_kq=None, shift=(0, 0, 0), band_lo=0, band_hi=-1) -> np.ndarray:
+    """W[n, m, k] = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 (n at k, m at k+q, relative to band_lo)
+    for eigenvectors c_k [Nk][no][nb] and the k+q data c_kq (same layout) or the mesh shift."""
+    lib = _load()
+    ck = _c128_as_f64(c_k)
+    nkt, no, nb = c_k.shape
+    lo, hi = int(band_lo), (nb if band_hi is None or band_hi < 0 else int(band_hi))
+    eps = np.zeros((nb, nkt))          # energies do not enter W
+    ckq = _c128_as_f64(c_kq)
+    out = np.zeros((hi - lo, hi - lo, nkt))
+    rc = lib.chi0_oracle_W(int(nk[0]), int(nk[1]), int(nk[2]), nb, no, _ptr(eps), _ptr(ck),
+                           _ptr(eps if c_kq is not None else None), _ptr(ckq), int(shift[0]), int(shift[1]),
+                           int(shift[2]), lo, hi, _ptr(out))
+    if rc != 0:
+        raise ValueError("chi0_oracle_W failed with code %d" % rc)
+    return out
+
+
+def matrix_elements(wl, q_index: int) -> np.ndarray:
+    """W of a synth.Workload at one of its q over its band window: [nbw][nbw][Nk]."""
+    q = wl.qs[q_index]
+    lo, hi = wl.window()
+    return matrix_elements_raw(wl.nk, wl.c_k, c_kq=q.c_kq, shift=q.shift if q.shift is not None else (0, 0, 0),
+                               band_lo=lo, band_hi=hi)
 
 
 def moments(wl, q_index: int, pmax: int = 6) -> np.ndarray:

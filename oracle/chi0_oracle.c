@@ -60,21 +60,28 @@ typedef double complex cplx;
 /* The function h(x) = (w-x)^3 Log(w-x+i0) and its derivatives               */
 /* ------------------------------------------------------------------------- */
 
-/* Log(u + i0): the branch of the retarded prescription. */
-static cplx log_retarded(double u)
+/* The frequency is complex, z = w + i eta with eta >= 0 (Eq. (1): the retarded response is the
+ * limit eta -> 0+ of the response at z).  u = z - x then lies in the closed upper half plane and
+ * Log is the principal branch: on the real axis (eta = 0, stored as +0) it is log|u| for u > 0 and
+ * log|u| + i pi for u < 0, the branch of w + i0. */
+static cplx log_upper(cplx u) { return clog(u); }
+
+/* u^k for a small integer k (negative k: 1/u^|k|), by repeated multiplication */
+static cplx cpowi(cplx u, int k)
 {
-    if (u > 0.0) return log(u);
-    return log(-u) + I * 3.14159265358979323846;
+    cplx r = 1.0;
+    for (int i = 0; i < (k < 0 ? -k : k); ++i) r *= u;
+    return k < 0 ? 1.0 / r : r;
 }
 
-/* h^{(n)}(x) / n!  at a point with u = w - x (x-derivatives).
+/* h^{(n)}(x) / n!  at a point with u = z - x (x-derivatives).
  *   h      =  u^3 L
  *   h'     = -(3 u^2 L + u^2)
  *   h''    =  6 u L + 5 u
  *   h'''   = -(6 L + 11)
  *   h^(n)  =  6 (n-4)! / u^(n-3)      (n >= 4)
  * At u = 0 the first three vanish and the rest diverge (NaN is returned). */
-static cplx hder_fact(int n, double u)
+static cplx hder_fact(int n, cplx u)
 {
     if (u == 0.0) {
         if (n <= 2) return 0.0;
@@ -82,9 +89,9 @@ static cplx hder_fact(int n, double u)
     }
     if (n >= 4) {
         double nn = (double)n;
-        return 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0) * pow(u, (double)(n - 3)));
+        return 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0) * cpowi(u, n - 3));
     }
-    cplx L = log_retarded(u);
+    cplx L = log_upper(u);
     switch (n) {
     case 0: return u * u * u * L;
     case 1: return -(3.0 * u * u * L + u * u);
@@ -95,58 +102,58 @@ static cplx hder_fact(int n, double u)
 
 /* Taylor sum  f[x_i..x_j] = sum_m h^{(p+m)}(c)/(p+m)! H_m(x_i - c, ..., x_j - c)
  * about the node c, H_m the complete homogeneous symmetric polynomial. */
-static cplx dd_taylor(const double *x, int i, int j, double c, double w)
+static cplx dd_taylor(const double *x, int i, int j, double c, cplx z)
 {
     int p = j - i;
-    double u = w - c;
-    double z[5];                       /* offsets from c, in units of u */
+    cplx u = z - c;
+    cplx y[5];                         /* offsets from c, in units of u */
     double rho = 0.0;
     for (int v = 0; v <= p; ++v) {
-        z[v] = (x[i + v] - c) / u;
-        if (fabs(z[v]) > rho) rho = fabs(z[v]);
+        y[v] = (x[i + v] - c) / u;
+        if (cabs(y[v]) > rho) rho = cabs(y[v]);
     }
     if (rho == 0.0) return hder_fact(p, u);      /* all nodes equal: h^(p)(c)/p! */
     /* number of terms: the bound C(m+p,p) rho^m falls below 1e-18 (at least 4 terms) */
     int M = 0;
     for (double b = 1.0; M < TAYLOR_MAX_TERMS && (M < 4 || b > 1e-18); ++M)
         b *= (double)(M + p + 1) / (double)(M + 1) * rho;
-    /* H[m] = H_m(z) of the scaled offsets, built up one variable at a time */
-    double H[TAYLOR_MAX_TERMS + 1];
+    /* H[m] = H_m(y) of the scaled offsets, built up one variable at a time */
+    cplx H[TAYLOR_MAX_TERMS + 1];
     H[0] = 1.0;
     for (int m = 1; m <= M; ++m) H[m] = 0.0;
     for (int v = 0; v <= p; ++v)
-        for (int m = 1; m <= M; ++m) H[m] += z[v] * H[m - 1];
+        for (int m = 1; m <= M; ++m) H[m] += y[v] * H[m - 1];
     /* h^{(n)}(c)/n! (x-c)^m-terms: for n = p+m >= 4 the coefficient is
      * 6/(n(n-1)(n-2)(n-3)) u^(3-n), and u^(3-n) u^m = u^(3-p). */
     cplx s = 0.0;
-    double up = pow(u, (double)(3 - p));
+    cplx up = cpowi(u, 3 - p);
     for (int m = M; m >= 0; --m) {
         int n = p + m;
         if (n >= 4) {
             double nn = (double)n;
             s += 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0)) * up * H[m];
         } else {
-            s += hder_fact(n, u) * pow(u, (double)m) * H[m];
+            s += hder_fact(n, u) * cpowi(u, m) * H[m];
         }
     }
     return s;
 }
 
 /* Divided difference h[x_i..x_j] over sorted nodes, memoised in tab/done. */
-static cplx dd_entry(const double *x, int i, int j, double w, cplx tab[5][5], int done[5][5])
+static cplx dd_entry(const double *x, int i, int j, cplx z, cplx tab[5][5], int done[5][5])
 {
     if (done[i][j]) return tab[i][j];
     cplx v;
     if (i == j) {
-        v = hder_fact(0, w - x[i]);
+        v = hder_fact(0, z - x[i]);
     } else {
         double span = x[j] - x[i];
-        double di = fabs(w - x[i]), dj = fabs(w - x[j]);
+        double di = cabs(z - x[i]), dj = cabs(z - x[j]);
         double far = di > dj ? di : dj;
         if (span <= THETA * far) {
-            v = dd_taylor(x, i, j, di >= dj ? x[i] : x[j], w);
+            v = dd_taylor(x, i, j, di >= dj ? x[i] : x[j], z);
         } else {
-            v = (dd_entry(x, i + 1, j, w, tab, done) - dd_entry(x, i, j - 1, w, tab, done)) / span;
+            v = (dd_entry(x, i + 1, j, z, tab, done) - dd_entry(x, i, j - 1, z, tab, done)) / span;
         }
     }
     tab[i][j] = v;
@@ -155,7 +162,7 @@ static cplx dd_entry(const double *x, int i, int j, double w, cplx tab[5][5], in
 }
 
 /* 5-node divided difference of h over arbitrary (unsorted) nodes. */
-static cplx dd5(const double nodes[5], double w)
+static cplx dd5(const double nodes[5], cplx z)
 {
     double x[5];
     memcpy(x, nodes, sizeof x);
@@ -168,15 +175,16 @@ static cplx dd5(const double nodes[5], double w)
     cplx tab[5][5];
     int done[5][5];
     memset(done, 0, sizeof done);
-    return dd_entry(x, 0, 4, w, tab, done);
+    return dd_entry(x, 0, 4, z, tab, done);
 }
 
-/* Corner weights J_j = h[D1,D2,D3,D4,D_j] of 1/(w - D + i0) on a simplex. */
-static void corner_weights(const double D[4], double w, cplx J[4])
+/* Corner weights J_j = h[D1,D2,D3,D4,D_j] of 1/(z - D) on a simplex (z = w + i0 on the real
+ * axis). */
+static void corner_weights(const double D[4], cplx z, cplx J[4])
 {
     for (int j = 0; j < 4; ++j) {
         double nodes[5] = {D[0], D[1], D[2], D[3], D[j]};
-        J[j] = dd5(nodes, w);
+        J[j] = dd5(nodes, z);
     }
 }
 
@@ -331,6 +339,7 @@ typedef struct {
     double mu;
     int cma, form;
     int single_carving; /* comparison only: first carving alone (see tet_contribution_at) */
+    double eta;         /* imaginary part of the frequency (0: the retarded limit on the real axis) */
     double *W; /* [nbw][nbw][nk] */
 } problem;
 
@@ -371,7 +380,7 @@ static void build_W(problem *P)
 /* Accumulate the contribution of one final tetrahedron (vertices in barycentric
  * coordinates) with sign s into acc[nw]. */
 static void add_piece(const btet *S, const double Dc[4], const double Wc[4], double s,
-                      int form, int nw, const double *omega, cplx *acc)
+                      int form, int nw, const double *omega, double eta, cplx *acc)
 {
     double v = btet_volume(S);
     if (v == 0.0) return;
@@ -383,11 +392,13 @@ static void add_piece(const btet *S, const double Dc[4], const double Wc[4], dou
     }
     for (int iw = 0; iw < nw; ++iw) {
         cplx J[4], sum = 0.0;
-        corner_weights(D, omega[iw], J);
+        const cplx z = omega[iw] + I * eta;
+        corner_weights(D, z, J);
         for (int j = 0; j < 4; ++j) sum += Wv[j] * J[j];
         if (form == 1) {
-            /* Eq. (1): 1/(w - D) + 1/(-w - D)  ==  1/(w - D) - 1/(w + D) */
-            corner_weights(Dm, omega[iw], J);
+            /* Eq. (1): 1/(w - D) + 1/(-w - D)  ==  1/(w - D) - 1/(w + D), both retarded (on the
+             * real axis only: the complex-frequency entry point takes form 0) */
+            corner_weights(Dm, z, J);
             for (int j = 0; j < 4; ++j) sum -= Wv[j] * J[j];
         }
         acc[iw] += s * v * sum;
@@ -427,14 +438,14 @@ static void tet_contribution_at(const problem *P, const long long idx[4], const 
                 memset(&T, 0, sizeof T);
                 for (int v = 0; v < 4; ++v) T.b[v][v] = 1.0;
                 int n1 = clip_negative(&T, fa, S);
-                for (int s = 0; s < n1; ++s) add_piece(&S[s], Dc, Wv, +1.0, 1, nw, omega, pacc);
+                for (int s = 0; s < n1; ++s) add_piece(&S[s], Dc, Wv, +1.0, 1, nw, omega, P->eta, pacc);
                 continue;
             }
             int ns = carve_region(a, b, 1, S);
-            for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, pacc);
+            for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, P->eta, pacc);
             if (P->form == 0) {
                 ns = carve_region(a, b, 2, S);
-                for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, pacc);
+                for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, P->eta, pacc);
             }
         }
 }
@@ -477,18 +488,20 @@ static int setup(problem *P, int n1, int n2, int n3, int nb, int no,
  * [cell_begin, cell_end) are summed (cell_end < 0: all), with the full-mesh
  * normalisation.  out: [nw][2] = (Re, Im).  Returns 0 on success.
  */
-int chi0_oracle(int n1, int n2, int n3, int nb, int no,
-                const double *eps_k, const double *c_k,
-                const double *eps_kq, const double *c_kq,
-                int s1, int s2, int s3,
-                double mu, double spin_factor, int band_lo, int band_hi,
-                int cma, int form, int nw, const double *omega,
-                long long cell_begin, long long cell_end, int nthreads, double *out)
+static int oracle_mesh(int n1, int n2, int n3, int nb, int no,
+                       const double *eps_k, const double *c_k,
+                       const double *eps_kq, const double *c_kq,
+                       int s1, int s2, int s3,
+                       double mu, double spin_factor, int band_lo, int band_hi,
+                       int cma, int form, int nw, const double *omega, double eta,
+                       long long cell_begin, long long cell_end, int nthreads, double *out)
 {
     problem P;
+    if (!(eta >= 0.0) || (eta > 0.0 && form != 0)) return -1;
     int rc = setup(&P, n1, n2, n3, nb, no, eps_k, c_k, eps_kq, c_kq, s1, s2, s3, mu,
                    band_lo, band_hi, cma, form);
     if (rc) return rc;
+    P.eta = eta;
     long long ncell = P.nk;
     if (cell_end < 0 || cell_end > ncell) cell_end = ncell;
     if (cell_begin < 0) cell_begin = 0;
@@ -522,6 +535,36 @@ int chi0_oracle(int n1, int n2, int n3, int nb, int no,
     free(acc);
     free(P.W);
     return 0;
+}
+
+int chi0_oracle(int n1, int n2, int n3, int nb, int no,
+                const double *eps_k, const double *c_k,
+                const double *eps_kq, const double *c_kq,
+                int s1, int s2, int s3,
+                double mu, double spin_factor, int band_lo, int band_hi,
+                int cma, int form, int nw, const double *omega,
+                long long cell_begin, long long cell_end, int nthreads, double *out)
+{
+    return oracle_mesh(n1, n2, n3, nb, no, eps_k, c_k, eps_kq, c_kq, s1, s2, s3, mu, spin_factor, band_lo,
+                       band_hi, cma, form, nw, omega, 0.0, cell_begin, cell_end, nthreads, out);
+}
+
+/*
+ * The same integral of the linear interpolant at the complex frequencies z = omega + i eta
+ * (eta >= 0, difference form only): sum W (f - f') / (z - D) integrated exactly over the carved
+ * final tetrahedra.  It is analytic in z in the upper half plane and tends to chi0_oracle's
+ * retarded result as eta -> 0+ (Eq. (1)); at finite eta it can be compared with plain k sums of
+ * the same Lorentzian-broadened expression, which converge without extrapolation in eta.
+ */
+int chi0_oracle_z(int n1, int n2, int n3, int nb, int no,
+                  const double *eps_k, const double *c_k,
+                  const double *eps_kq, const double *c_kq,
+                  int s1, int s2, int s3,
+                  double mu, double spin_factor, int band_lo, int band_hi,
+                  int cma, int nw, const double *omega, double eta, int nthreads, double *out)
+{
+    return oracle_mesh(n1, n2, n3, nb, no, eps_k, c_k, eps_kq, c_kq, s1, s2, s3, mu, spin_factor, band_lo,
+                       band_hi, cma, 0, nw, omega, eta, 0, -1, nthreads, out);
 }
 
 /*
@@ -725,14 +768,14 @@ int chi0_oracle_moments(int n1, int n2, int n3, int nb, int no,
 void chi0_oracle_weights(const double *D, double w, double *J)
 {
     cplx Jc[4];
-    corner_weights(D, w, Jc);
+    corner_weights(D, w + 0.0 * I, Jc);
     for (int j = 0; j < 4; ++j) { J[2 * j] = creal(Jc[j]); J[2 * j + 1] = cimag(Jc[j]); }
 }
 
 /* 5-node divided difference of h(x) = (w-x)^3 Log(w-x+i0) */
 void chi0_oracle_dd5(const double *nodes, double w, double *out)
 {
-    cplx v = dd5(nodes, w);
+    cplx v = dd5(nodes, w + 0.0 * I);
     out[0] = creal(v);
     out[1] = cimag(v);
 }
@@ -755,4 +798,21 @@ void chi0_oracle_tet_corners(int n1, int n2, int n3, long long cell, int t, long
 {
     int n[3] = {n1, n2, n3};
     tet_corners(n, cell, t, idx);
+}
+
+/* The matrix-element weights the integration interpolates (footnote of Sec. III, with n at k
+ * and m at k+q): W[(n*nbw + m)*Nk + k] = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for n, m
+ * relative to band_lo.  Arguments as for chi0_oracle (not under CMA).  Returns 0 on success. */
+int chi0_oracle_W(int n1, int n2, int n3, int nb, int no,
+                  const double *eps_k, const double *c_k,
+                  const double *eps_kq, const double *c_kq,
+                  int s1, int s2, int s3, int band_lo, int band_hi, double *W)
+{
+    problem P;
+    int rc = setup(&P, n1, n2, n3, nb, no, eps_k, c_k, eps_kq, c_kq, s1, s2, s3, 0.0,
+                   band_lo, band_hi, 0, 0);
+    if (rc) return rc;
+    memcpy(W, P.W, sizeof(double) * (size_t)P.nbw * P.nbw * P.nk);
+    free(P.W);
+    return 0;
 }
