@@ -71,7 +71,7 @@ PW_TRAFFIC_KERNEL_SHA = "a205e9b07bc4afcf"
 PW_TRAFFIC_BYTES_PER_LAUNCH = (33201068 * 2.0 + 989042 * 1.0) * 1024
 
 
-def kernel_sha(files=("k_tetra.hip", "chi0_math.h")) -> str:
+def kernel_sha(files=("k_tetra.h", "k_tetra_dyn.hip", "chi0_math.h")) -> str:
     import hashlib
     h = hashlib.sha256()
     for f in files:

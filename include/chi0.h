@@ -35,6 +35,16 @@
  *   * Errors: every call returns a chi0_status; descriptor and argument checks are
  *     done on the host before anything is enqueued.  A failure reported by the HIP
  *     runtime is returned as CHI0_E_DEVICE.  No exception crosses the ABI.
+ *   * Content checks (Sec. II takes band energies and normalised eigenvectors as inputs): unless
+ *     the descriptor sets skip_input_scan, every computing call of a plan first enqueues a scan
+ *     of the device arrays it reads -- eps_k, c_k, the explicit k+q arrays of its q-points and
+ *     omega -- for non-finite values and for eigenvectors whose squared norm
+ *     sum_o |c_{o,n}(k)|^2 differs from 1 by more than 1e-6.  The scan runs on the stream
+ *     ahead of the computation and does not stop it; its verdict is reported asynchronously:
+ *     by the plan's next call once the scan has completed (that call then returns
+ *     CHI0_E_NONFINITE or CHI0_E_NOT_NORMALIZED and enqueues nothing), or by chi0_sync.  The
+ *     outputs of a call whose scan failed are not meaningful.  chi0_matrix_elements and the
+ *     batched form do not scan.
  *   * A plan is not thread safe: use one plan per host thread.
  *   * If a final tetrahedron has a whole face on which e' - e equals w (e.g. an
  *     exactly nested tetrahedron at w = 0), the integral diverges and the output
@@ -54,12 +64,15 @@ typedef enum chi0_status {
     CHI0_OK = 0,
     CHI0_E_INVALID_ARG = -1,   /* null pointer, bad enum value, negative count */
     CHI0_E_SHAPE = -2,         /* mesh, band, orbital or window sizes out of range */
-    CHI0_E_NONFINITE = -3,     /* mu, the spin factor or a spectral range is not finite (device
-                                  arrays are not scanned: a non-finite omega gives a non-finite
-                                  result at that frequency only) */
+    CHI0_E_NONFINITE = -3,     /* host values (mu, the spin factor, the degeneracy tolerances, q_frac,
+                                  a spectral range) not finite; or, from the device scan, a
+                                  non-finite band energy, eigenvector coefficient or frequency */
+    CHI0_E_NOT_COMMENSURATE = -4, /* a q given by q_frac alone (explicit_kq = 2) is not a mesh vector */
     CHI0_E_WORKSPACE = -5,     /* workspace null or smaller than chi0_workspace_size */
     CHI0_E_DEVICE = -6,        /* the HIP runtime reported an error */
-    CHI0_E_UNSUPPORTED = -7    /* valid request outside what this build implements */
+    CHI0_E_UNSUPPORTED = -7,   /* valid request outside what this build implements */
+    CHI0_E_NOT_NORMALIZED = -8 /* device scan: an eigenvector's squared norm differs from 1 by more
+                                  than 1e-6 */
 } chi0_status;
 
 /* Problem description, copied by chi0_plan. */
@@ -80,23 +93,38 @@ typedef struct chi0_desc {
                                1: mixed: matrix elements from BF16 MFMA with hi+lo split operands
                                   and FP32 accumulation; dynamic weights of final tetrahedra in
                                   FP32 (far series and near branch), except that near-degenerate
-                                  final tetrahedra (two corner values of e'-e within 1e-6 energy
-                                  units) keep the FP64 near branch; carving, differences of
-                                  energies and the chi0 accumulation stay FP64.
+                                  final tetrahedra (degen_tol_ev, degen_rel_tol below) keep the
+                                  FP64 near branch; carving, differences of energies and the chi0
+                                  accumulation stay FP64.
                                2: as 1 with FP16 (low part scaled by 2^11) instead of BF16. */
-    int32_t reserved[5];    /* must be zero */
+    int32_t batch_hint;     /* q-points per launch sequence, 1..16 (0 = 16): the workspace holds the
+                               matrix elements and partial sums of that many q at once, so a
+                               smaller value trades launches for memory */
+    int32_t skip_input_scan; /* 0: scan the device inputs of every call (see Content checks);
+                               1: do not scan */
+    int32_t reserved[3];    /* must be zero */
     double mu;              /* Fermi level (energy units of the band arrays) */
     double spin_factor;     /* g_s, 2 for spin-degenerate bands */
+    double degen_tol_ev;    /* mixed form: a final tetrahedron whose sorted corner values of e'-e
+                               have two neighbours closer than max(degen_tol_ev, degen_rel_tol x
+                               their span) is near-degenerate and keeps the FP64 near branch.
+                               Energy units of the band arrays; >= 0, 0 selects 1e-6 */
+    double degen_rel_tol;   /* the relative part of the rule above, >= 0 (0: absolute rule only) */
 } chi0_desc;
 
 /* One q.  Either an integer mesh shift (k+q data = mesh data at (i + shift) mod N),
  * or explicit band data at k+q for every mesh point k. */
 typedef struct chi0_q {
     int32_t shift[3];       /* used when explicit_kq == 0 */
-    int32_t explicit_kq;    /* 1: eps_kq / c_kq below hold the k+q data */
+    int32_t explicit_kq;    /* 0: mesh shift `shift`;
+                               1: eps_kq / c_kq below hold the k+q data;
+                               2: mesh shift derived from q_frac: q_frac[a] * N_a must be an integer
+                                  to 1e-9 relative (else CHI0_E_NOT_COMMENSURATE) */
     const double *eps_kq;   /* device [n_bands][Nk] float64, energies at k+q */
     const double *c_kq;     /* device [Nk][n_orb][n_bands] complex128 (re,im), eigenvectors at
                                k+q; may be NULL under cma */
+    double q_frac[3];       /* q in fractional reciprocal coordinates: defines the shift when
+                               explicit_kq = 2, informational otherwise (not read) */
 } chi0_q;
 
 typedef struct chi0_plan_s *chi0_plan_t;
@@ -205,6 +233,11 @@ chi0_status chi0_dynamic_group(chi0_plan_t plan, int32_t nq, int32_t n_group, co
  * the sizes. */
 chi0_status chi0_iw_cubic(int32_t n, int64_t *n_kp, int64_t *n_tet, double *volume, double *kfrac,
                           int32_t *tets, int32_t *ops);
+
+/* Wait for the plan's stream and report the verdict of every input scan enqueued since the last
+ * report (see Content checks): CHI0_OK, CHI0_E_NONFINITE or CHI0_E_NOT_NORMALIZED (chi0_last_error
+ * names the input), or CHI0_E_DEVICE if the stream failed. */
+chi0_status chi0_sync(chi0_plan_t plan);
 
 /* Kernel timing of the plan's launches, measured with HIP events on the plan's stream
  * while profiling is enabled.  Index 0: matrix-element kernel, 1: tetrahedron kernel,

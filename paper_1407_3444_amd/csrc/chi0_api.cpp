@@ -19,6 +19,7 @@
 
 #include "chi0_host.h"
 #include "chi0_internal.h"
+#include "chi0_math.h"
 
 using namespace chi0;
 
@@ -27,15 +28,26 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 
+// Verdict slots of the asynchronous input scans: each call's verdict word is copied from the
+// workspace into one pinned host word, whose event says when it has landed.
+constexpr int kScanSlots = 8;
+
 struct chi0_plan_s {
     chi0_desc d;
     MeshDev mesh;
     bool list = false;      // tetrahedron-list plan: explicit q only, prefactor spin_factor * volume
     double volume = 0.0;
+    int qbatch = kMaxQBatch;   // q-points per launch sequence (batch_hint)
     hipStream_t stream;
     std::string err;
     bool profiling = false;
     std::vector<TimedLaunch> events;
+    // input scans (allocated at plan creation when a device is present)
+    unsigned *scan_host = nullptr;          // pinned [kScanSlots]
+    hipEvent_t scan_ev[kScanSlots] = {};
+    bool scan_pending[kScanSlots] = {};
+    int scan_next = 0;
+    unsigned scan_bits = 0;                 // verdicts landed and not yet reported
 };
 
 namespace {
@@ -56,6 +68,117 @@ chi0_status device_fail(chi0_plan_t p, hipError_t e, const char *where)
         p->err = std::string(where) + ": " + hipGetErrorString(e);
     }
     return CHI0_E_DEVICE;
+}
+
+// Pinned verdict words and their events; without a device the plan simply has none (every
+// computing call then fails at its first launch anyway).
+void scan_setup(chi0_plan_s *p)
+{
+    if (p->d.skip_input_scan) return;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, sizeof(unsigned) * kScanSlots, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    for (int i = 0; i < kScanSlots; ++i) {
+        if (hipEventCreateWithFlags(&p->scan_ev[i], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->scan_ev[j]);
+            (void)hipHostFree(h);
+            return;
+        }
+    }
+    p->scan_host = static_cast<unsigned *>(h);
+}
+
+void scan_release(chi0_plan_s *p)
+{
+    if (!p->scan_host) return;
+    for (int i = 0; i < kScanSlots; ++i) (void)hipEventDestroy(p->scan_ev[i]);
+    (void)hipHostFree(p->scan_host);
+    p->scan_host = nullptr;
+}
+
+// Collect the verdicts that have landed (all of them, waiting, when block is set).
+void scan_collect(chi0_plan_s *p, bool block)
+{
+    if (!p->scan_host) return;
+    for (int k = 0; k < kScanSlots; ++k) {
+        const int i = (p->scan_next + k) % kScanSlots;     // oldest first
+        if (!p->scan_pending[i]) continue;
+        const hipError_t e = block ? hipEventSynchronize(p->scan_ev[i]) : hipEventQuery(p->scan_ev[i]);
+        if (e == hipErrorNotReady) continue;
+        p->scan_pending[i] = false;
+        if (e == hipSuccess) p->scan_bits |= p->scan_host[i];
+    }
+}
+
+// The status for collected verdicts (consumed), CHI0_OK if none.
+chi0_status scan_report(chi0_plan_s *p)
+{
+    const unsigned b = p->scan_bits;
+    if (!b) return CHI0_OK;
+    p->scan_bits = 0;
+    std::string what;
+    if (b & kScanEps) what += " band energies;";
+    if (b & kScanEig) what += " eigenvector coefficients;";
+    if (b & kScanOmega) what += " frequencies;";
+    if (b & (kScanEps | kScanEig | kScanOmega)) {
+        p->err = "input scan of an earlier call: non-finite" + what;
+        if (b & kScanNorm) p->err += " and eigenvectors not normalised";
+        return CHI0_E_NONFINITE;
+    }
+    p->err = "input scan of an earlier call: an eigenvector's squared norm differs from 1 by more than 1e-6";
+    return CHI0_E_NOT_NORMALIZED;
+}
+
+// Start of every computing call: report a verdict of an earlier scan that has landed.
+chi0_status begin_call(chi0_plan_s *p)
+{
+    scan_collect(p, false);
+    return scan_report(p);
+}
+
+// Enqueue the scan of the inputs of one call: mesh arrays, the explicit k+q arrays of qs (each
+// distinct array once) and omega; the verdict word sits in the workspace at flag.
+chi0_status enqueue_scan(chi0_plan_s *p, int nq, const chi0_q *qs, const double *omega, int nw, unsigned *flag)
+{
+    if (p->d.skip_input_scan || !p->scan_host) return CHI0_OK;
+    const int slot = p->scan_next;
+    if (p->scan_pending[slot]) {           // the ring is full: wait for its oldest verdict
+        const hipError_t e = hipEventSynchronize(p->scan_ev[slot]);
+        if (e != hipSuccess) return device_fail(p, e, "input scan");
+        p->scan_pending[slot] = false;
+        p->scan_bits |= p->scan_host[slot];
+    }
+    const MeshDev &M = p->mesh;
+    const double tol = 1e-6;
+    hipError_t e = launch_scan_clear(flag, p->stream);
+    if (e == hipSuccess) e = launch_scan_finite(M.eps_k, (int64_t)M.nb * M.nk, kScanEps, flag, p->stream);
+    if (e == hipSuccess && !M.cma)
+        e = launch_scan_eigvec(M.c_k, M.nk, M.no, M.nb, kScanEig, kScanNorm, tol, flag, p->stream);
+    std::vector<const void *> seen;
+    for (int i = 0; i < nq && e == hipSuccess; ++i) {
+        if (qs[i].explicit_kq != 1) continue;
+        const void *key = qs[i].eps_kq;
+        if (std::find(seen.begin(), seen.end(), key) == seen.end()) {
+            seen.push_back(key);
+            e = launch_scan_finite(qs[i].eps_kq, (int64_t)M.nb * M.nk, kScanEps, flag, p->stream);
+        }
+        if (e == hipSuccess && !M.cma && qs[i].c_kq &&
+            std::find(seen.begin(), seen.end(), (const void *)qs[i].c_kq) == seen.end()) {
+            seen.push_back(qs[i].c_kq);
+            e = launch_scan_eigvec(qs[i].c_kq, M.nk, M.no, M.nb, kScanEig, kScanNorm, tol, flag, p->stream);
+        }
+    }
+    if (e == hipSuccess && omega) e = launch_scan_finite(omega, nw, kScanOmega, flag, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&p->scan_host[slot], flag, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->scan_ev[slot], p->stream);
+    if (e != hipSuccess) return device_fail(p, e, "input scan");
+    p->scan_pending[slot] = true;
+    p->scan_next = (slot + 1) % kScanSlots;
+    return CHI0_OK;
 }
 
 int64_t n_units(const chi0_plan_s *p)
@@ -84,14 +207,14 @@ int n_blocks_pair(const chi0_plan_s *p)
 }
 
 struct Layout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, count_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, count_off, flag_off, total;
     int qbatch;
 };
 
 Layout layout(const chi0_plan_s *p, int nq, int nvals)
 {
     Layout L;
-    L.qbatch = std::min(nq, kMaxQBatch);
+    L.qbatch = std::min(nq, p->qbatch);
     L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
     // the partial sums of a dynamic or static call, or of a pair-resolved static call
     const size_t npairs = (size_t)p->mesh.nbw * p->mesh.nbw;
@@ -100,22 +223,28 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals)
     L.w_off = 0;
     L.part_off = L.w_bytes_per_q * L.qbatch;
     L.count_off = L.part_off + L.part_bytes_per_q * L.qbatch;
-    L.total = L.count_off + kAlign;       // census counters
+    L.flag_off = L.count_off + 128;       // census counters (40 bytes), then the scan verdict
+    L.total = L.count_off + kAlign;
     return L;
+}
+
+unsigned *scan_flag(void *ws, const Layout &L)
+{
+    return reinterpret_cast<unsigned *>(static_cast<char *>(ws) + L.flag_off);
 }
 
 // Workspace of the Kramers-Kronig route: W and the partial sums as for a dynamic call (up to
 // kMaxOmegaIm frequencies per launch), then the frequency list (grid and requested) and the
 // imaginary part on it for one batch of q.
 struct KKLayout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, om_off, im_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, om_off, im_off, flag_off, total;
     int qbatch, n_all;
 };
 
 KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
 {
     KKLayout L;
-    L.qbatch = std::min(nq, kMaxQBatch);
+    L.qbatch = std::min(nq, p->qbatch);
     L.n_all = K + nw;
     L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
     L.part_bytes_per_q = align_up(sizeof(double) * (size_t)n_blocks(p) * 2 * std::min(L.n_all, kMaxOmegaIm));
@@ -123,7 +252,8 @@ KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
     L.part_off = L.w_bytes_per_q * L.qbatch;
     L.om_off = L.part_off + L.part_bytes_per_q * L.qbatch;
     L.im_off = L.om_off + align_up(sizeof(double) * (size_t)L.n_all);
-    L.total = L.im_off + align_up(sizeof(double) * 2 * (size_t)L.n_all * L.qbatch);
+    L.flag_off = L.im_off + align_up(sizeof(double) * 2 * (size_t)L.n_all * L.qbatch);
+    L.total = L.flag_off + kAlign;
     return L;
 }
 
@@ -134,7 +264,7 @@ chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
         const char *msg = "";
         const chi0_status st = check_q(p->d, qs[i], &msg);
         if (st) return fail(p, st, msg);
-        if (p->list && !qs[i].explicit_kq)
+        if (p->list && qs[i].explicit_kq != 1)
             return fail(p, CHI0_E_INVALID_ARG, "a tetrahedron-list plan takes explicit k+q data only");
     }
     return CHI0_OK;
@@ -147,19 +277,19 @@ struct GroupLaunch {
     bool accumulate;
 };
 
-std::vector<GroupLaunch> group_launches(int nq, int n_group)
+std::vector<GroupLaunch> group_launches(int nq, int n_group, int qbatch)
 {
     std::vector<GroupLaunch> out;
-    if (n_group <= kMaxQBatch) {
-        const int per = kMaxQBatch / n_group;
+    if (n_group <= qbatch) {
+        const int per = qbatch / n_group;
         for (int g0 = 0; g0 < nq; g0 += per) {
             const int ng = std::min(per, nq - g0);
             out.push_back({g0 * n_group, ng * n_group, g0, ng, false});
         }
     } else {
         for (int g = 0; g < nq; ++g)
-            for (int c0 = 0; c0 < n_group; c0 += kMaxQBatch)
-                out.push_back({g * n_group + c0, std::min(kMaxQBatch, n_group - c0), g, 1, c0 > 0});
+            for (int c0 = 0; c0 < n_group; c0 += qbatch)
+                out.push_back({g * n_group + c0, std::min(qbatch, n_group - c0), g, 1, c0 > 0});
     }
     return out;
 }
@@ -210,9 +340,14 @@ chi0_status check_desc(const chi0_desc *d, const double *eps_k, const double *c_
     if (d->cma != 0 && d->cma != 1) return CHI0_E_INVALID_ARG;
     if (!d->cma && (d->n_orb < 1 || d->n_orb > kMaxOrb)) return CHI0_E_SHAPE;
     if (d->form != 0 && d->form != 1) return CHI0_E_INVALID_ARG;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 3; ++i)
         if (d->reserved[i] != 0) return CHI0_E_INVALID_ARG;
-    if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor)) return CHI0_E_NONFINITE;
+    if (d->batch_hint < 0 || d->batch_hint > kMaxQBatch) return CHI0_E_INVALID_ARG;
+    if (d->skip_input_scan != 0 && d->skip_input_scan != 1) return CHI0_E_INVALID_ARG;
+    if (!std::isfinite(d->mu) || !std::isfinite(d->spin_factor) || !std::isfinite(d->degen_tol_ev) ||
+        !std::isfinite(d->degen_rel_tol))
+        return CHI0_E_NONFINITE;
+    if (d->degen_tol_ev < 0.0 || d->degen_rel_tol < 0.0) return CHI0_E_INVALID_ARG;
     if (d->precision < 0 || d->precision > 2) return CHI0_E_INVALID_ARG;
     if (!eps_k) return CHI0_E_INVALID_ARG;
     if (!d->cma && !c_k) return CHI0_E_INVALID_ARG;
@@ -240,16 +375,44 @@ MeshDev make_mesh(const chi0_desc &d, const double *eps_k, const double *c_k)
     M.ncell = M.nk;
     M.nperm = 6;
     M.tets = nullptr;
+    M.degen_tol = d.degen_tol_ev > 0.0 ? d.degen_tol_ev : kDegenerateTol;
+    M.degen_rel = d.degen_rel_tol;
     return M;
+}
+
+// Mesh shift of a q given by q_frac: q_frac[a] * N_a rounded, when it is an integer to 1e-9
+// relative; false otherwise.
+bool shift_from_frac(const chi0_desc &d, const chi0_q &q, int32_t shift[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const double x = q.q_frac[a] * (double)d.nk[a];
+        const double r = std::nearbyint(x);
+        if (!(std::fabs(x - r) <= 1e-9 * std::max(1.0, std::fabs(x)))) return false;
+        const double m = std::fmod(r, (double)d.nk[a]);
+        shift[a] = (int32_t)(m < 0 ? m + d.nk[a] : m);
+    }
+    return true;
 }
 
 chi0_status check_q(const chi0_desc &d, const chi0_q &q, const char **msg)
 {
-    if (q.explicit_kq != 0 && q.explicit_kq != 1) {
-        *msg = "explicit_kq must be 0 or 1";
+    if (q.explicit_kq < 0 || q.explicit_kq > 2) {
+        *msg = "explicit_kq must be 0, 1 or 2";
         return CHI0_E_INVALID_ARG;
     }
-    if (q.explicit_kq) {
+    if (q.explicit_kq == 2) {
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(q.q_frac[a])) {
+                *msg = "q_frac not finite";
+                return CHI0_E_NONFINITE;
+            }
+        int32_t s[3];
+        if (!shift_from_frac(d, q, s)) {
+            *msg = "q_frac is not a vector of the mesh";
+            return CHI0_E_NOT_COMMENSURATE;
+        }
+    }
+    if (q.explicit_kq == 1) {
         if (!q.eps_kq) {
             *msg = "explicit q without eps_kq";
             return CHI0_E_INVALID_ARG;
@@ -267,14 +430,22 @@ QDev make_qdev(const MeshDev &M, const chi0_q &q, double *W)
     QDev d;
     std::memset(&d, 0, sizeof d);
     const int n[3] = {M.n1, M.n2, M.n3};
-    d.explicit_kq = q.explicit_kq;
-    if (q.explicit_kq) {
+    d.explicit_kq = q.explicit_kq == 1 ? 1 : 0;
+    if (q.explicit_kq == 1) {
         d.eps_kq = q.eps_kq;
         d.c_kq = q.c_kq;
     } else {
         d.eps_kq = M.eps_k;
         d.c_kq = M.c_k;
-        for (int a = 0; a < 3; ++a) d.shift[a] = ((q.shift[a] % n[a]) + n[a]) % n[a];
+        int32_t s[3] = {q.shift[0], q.shift[1], q.shift[2]};
+        if (q.explicit_kq == 2) {
+            chi0_desc dd;
+            std::memset(&dd, 0, sizeof dd);
+            dd.nk[0] = M.n1; dd.nk[1] = M.n2; dd.nk[2] = M.n3;
+            shift_from_frac(dd, q, s);     // validated by check_q
+        }
+        d.explicit_kq = 0;
+        for (int a = 0; a < 3; ++a) d.shift[a] = ((s[a] % n[a]) + n[a]) % n[a];
     }
     d.W = M.cma ? nullptr : W;
     return d;
@@ -294,6 +465,8 @@ const char *chi0_status_string(chi0_status s)
     case CHI0_E_WORKSPACE: return "workspace too small";
     case CHI0_E_DEVICE: return "device error";
     case CHI0_E_UNSUPPORTED: return "unsupported";
+    case CHI0_E_NOT_COMMENSURATE: return "q not commensurate with the mesh";
+    case CHI0_E_NOT_NORMALIZED: return "eigenvectors not normalised";
     }
     return "unknown status";
 }
@@ -311,7 +484,9 @@ chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *d, const double *eps_k,
     p->d = *d;
     p->mesh = make_mesh(*d, eps_k, c_k);
     p->d.band_hi = p->mesh.lo + p->mesh.nbw;
+    p->qbatch = d->batch_hint > 0 ? d->batch_hint : kMaxQBatch;
     p->stream = static_cast<hipStream_t>(stream);
+    scan_setup(p);
     *out = p;
     return CHI0_OK;
 }
@@ -350,7 +525,9 @@ chi0_status chi0_plan_list(chi0_plan_t *out, const chi0_desc *d, const chi0_tetr
     p->list = true;
     p->volume = list->volume;
     p->d.band_hi = p->mesh.lo + p->mesh.nbw;
+    p->qbatch = d->batch_hint > 0 ? d->batch_hint : kMaxQBatch;
     p->stream = hs;
+    scan_setup(p);
     *out = p;
     return CHI0_OK;
 }
@@ -362,9 +539,20 @@ chi0_status chi0_destroy(chi0_plan_t p)
             (void)hipEventDestroy(t.start);
             (void)hipEventDestroy(t.stop);
         }
+        scan_collect(p, true);
+        scan_release(p);
     }
     delete p;
     return CHI0_OK;
+}
+
+chi0_status chi0_sync(chi0_plan_t p)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    const hipError_t e = hipStreamSynchronize(p->stream);
+    scan_collect(p, true);
+    if (e != hipSuccess) return device_fail(p, e, "stream");
+    return scan_report(p);
 }
 
 chi0_status chi0_profile_enable(chi0_plan_t p, int32_t enable)
@@ -397,13 +585,16 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
                         size_t ws_bytes, uint64_t *counts)
 {
     if (!p) return CHI0_E_INVALID_ARG;
-    chi0_status st = check_qs(p, nq, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, nq, qs);
     if (st) return st;
     if (nw < 1 || !omega || !counts) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and counts required");
     const Layout L = layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch));
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
     hipError_t e = hipMemsetAsync(dc, 0, 5 * sizeof(unsigned long long), p->stream);
     if (e != hipSuccess) return device_fail(p, e, "census clear");
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
@@ -437,13 +628,16 @@ chi0_status chi0_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, size_t *b
 chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, size_t ws_bytes, double *chi)
 {
     if (!p) return CHI0_E_INVALID_ARG;
-    chi0_status st = check_qs(p, nq, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, nq, qs);
     if (st) return st;
     if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
     const Layout L = layout(p, nq, 1);
     size_t need = 0;
     chi0_workspace_size(p, nq, 1, &need);
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    if ((st = enqueue_scan(p, nq, qs, nullptr, 0, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
@@ -468,11 +662,14 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
 chi0_status chi0_static_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, size_t ws_bytes, double *chi)
 {
     if (!p) return CHI0_E_INVALID_ARG;
-    chi0_status st = check_qs(p, nq, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, nq, qs);
     if (st) return st;
     if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
     const Layout L = layout(p, nq, 1);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    if ((st = enqueue_scan(p, nq, qs, nullptr, 0, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks_pair(p);
     const int npairs = p->mesh.nbw * p->mesh.nbw;
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
@@ -500,7 +697,9 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
                          size_t ws_bytes, double *chi)
 {
     if (!p) return CHI0_E_INVALID_ARG;
-    chi0_status st = check_qs(p, nq, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, nq, qs);
     if (st) return st;
     if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
@@ -508,6 +707,7 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
     size_t need = 0;
     chi0_workspace_size(p, nq, nw, &need);
     if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
@@ -549,7 +749,9 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
                             int32_t n_spec, double spec_lo, double spec_hi, void *ws, size_t ws_bytes, double *chi)
 {
     if (!p) return CHI0_E_INVALID_ARG;
-    chi0_status st = check_qs(p, nq, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, nq, qs);
     if (st) return st;
     if (nw < 1 || !omega || !chi || n_spec < 2)
         return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, n_spec >= 2, omega and chi non-null required");
@@ -560,6 +762,8 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
     const KKLayout L = kk_layout(p, nq, nw, n_spec);
     if (!ws || ws_bytes < need) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     char *base = static_cast<char *>(ws);
+    if ((st = enqueue_scan(p, nq, qs, omega, nw, reinterpret_cast<unsigned *>(base + L.flag_off))) != CHI0_OK)
+        return st;
     double *partial = reinterpret_cast<double *>(base + L.part_off);
     double *om_all = reinterpret_cast<double *>(base + L.om_off);
     double *im_all = reinterpret_cast<double *>(base + L.im_off);
@@ -604,15 +808,18 @@ chi0_status chi0_static_group(chi0_plan_t p, int32_t nq, int32_t n_group, const 
     if (nq < 1 || n_group < 1 || (int64_t)nq * n_group >= (int64_t(1) << 31))
         return fail(p, CHI0_E_INVALID_ARG, "nq and n_group must be >= 1");
     const int ne = nq * n_group;
-    chi0_status st = check_qs(p, ne, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, ne, qs);
     if (st) return st;
     if (!chi) return fail(p, CHI0_E_INVALID_ARG, "chi is null");
     const Layout L = layout(p, ne, 1);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    if ((st = enqueue_scan(p, ne, qs, nullptr, 0, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
-    for (const GroupLaunch &G : group_launches(nq, n_group)) {
+    for (const GroupLaunch &G : group_launches(nq, n_group, p->qbatch)) {
         BatchDev B;
         fill_batch(p, qs, G.e0, G.ne, ws, L, B);
         const int per_group = G.ne / G.ng;
@@ -639,16 +846,19 @@ chi0_status chi0_dynamic_group(chi0_plan_t p, int32_t nq, int32_t n_group, const
     if (nq < 1 || n_group < 1 || (int64_t)nq * n_group >= (int64_t(1) << 31))
         return fail(p, CHI0_E_INVALID_ARG, "nq and n_group must be >= 1");
     const int ne = nq * n_group;
-    chi0_status st = check_qs(p, ne, qs);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, ne, qs);
     if (st) return st;
     if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
     const Layout L = layout(p, ne, 2 * nwc_max);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    if ((st = enqueue_scan(p, ne, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
-    for (const GroupLaunch &G : group_launches(nq, n_group)) {
+    for (const GroupLaunch &G : group_launches(nq, n_group, p->qbatch)) {
         BatchDev B;
         fill_batch(p, qs, G.e0, G.ne, ws, L, B);
         const int per_group = G.ne / G.ng;
@@ -678,7 +888,9 @@ chi0_status chi0_matrix_elements(chi0_plan_t p, const chi0_q *q, double *W)
 {
     if (!p) return CHI0_E_INVALID_ARG;
     if (p->d.cma) return fail(p, CHI0_E_UNSUPPORTED, "no matrix elements under cma");
-    chi0_status st = check_qs(p, 1, q);
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    st = check_qs(p, 1, q);
     if (st) return st;
     if (!W) return fail(p, CHI0_E_INVALID_ARG, "W is null");
     Layout L = layout(p, 1, 1);

@@ -96,6 +96,12 @@ chi0_status validate(int32_t n_inst, const chi0_instance *inst, const chi0_batch
             err = "instance " + std::to_string(i) + ": invalid description";
             return st;
         }
+        if (!I.desc.cma && I.desc.n_orb > kMaxOrbSmall) {
+            // the fused matrix-element launch has the small-basis tiles only
+            err = "instance " + std::to_string(i) + ": bases above " + std::to_string(kMaxOrbSmall) +
+                  " functions (plane waves) are not supported in the batched form";
+            return CHI0_E_UNSUPPORTED;
+        }
         if (I.nq < 1 || I.nw < 1 || !I.qs || !I.omega || !I.chi) {
             err = "instance " + std::to_string(i) + ": nq, nw >= 1 and qs, omega, chi non-null required";
             return CHI0_E_INVALID_ARG;

@@ -42,6 +42,9 @@ struct MeshDev {
     int64_t ncell;
     int32_t nperm;
     const int32_t *tets;
+    // mixed form: near-degenerate final tetrahedra (two sorted corner values of e'-e closer than
+    // max(degen_tol, degen_rel * span)) keep the FP64 near branch
+    double degen_tol, degen_rel;
 };
 
 // Tetrahedra per band pair.
@@ -100,6 +103,8 @@ hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch,
 // mixed: far-branch series in FP32 (FP64 near branch and accumulation).
 hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
                                 const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
+hipError_t launch_tetra_dynamic_list(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
+                                     const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 
 // Census of the work of a dynamic call (nw <= kMaxOmegaPerLaunch), by the dynamic evaluation
 // itself with counters (it also writes the call's partial sums): counts[0..4] += active units,
@@ -110,6 +115,15 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
 hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
                          int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,
                          hipStream_t s);
+
+// Content scan of device inputs: clear the verdict word, then OR bits into it for non-finite
+// values of a float64 array, and for eigenvectors c[Nk][no][nb] (complex) with non-finite
+// coefficients or a squared norm off 1 by more than tol.
+constexpr unsigned kScanEps = 1u, kScanEig = 2u, kScanOmega = 4u, kScanNorm = 8u;
+hipError_t launch_scan_clear(unsigned *flag, hipStream_t s);
+hipError_t launch_scan_finite(const double *p, int64_t n, unsigned bit, unsigned *flag, hipStream_t s);
+hipError_t launch_scan_eigvec(const double *c, int64_t nk, int no, int nb, unsigned bit_nonfinite, unsigned bit_norm,
+                              double tol, unsigned *flag, hipStream_t s);
 
 // K_R: out[q * out_stride + v] = scale * sum_b partial[(q * nblocks + b) * nvals + v], fixed order.
 hipError_t launch_reduce(const double *partial, int nq, int nblocks, int nvals, double scale,

@@ -611,12 +611,13 @@ C0_HD double near_im(const double y[4], const double w[4], double om)
 }
 
 // Mixed form: a final tetrahedron whose sorted corner values have two neighbours closer than
-// tol (or that is flat) keeps the FP64 near branch; kDegenerateTol in the energy unit of the
-// band arrays (eV for the supplied models).
+// max(tol, rel * span) (or that is flat) keeps the FP64 near branch; tol in the energy unit of the
+// band arrays (default kDegenerateTol, 1e-6: eV for the supplied models).
 constexpr double kDegenerateTol = 1e-6;
-C0_HD bool near_degenerate(const double y[4], double tol)
+C0_HD bool near_degenerate(const double y[4], double tol, double rel = 0.0)
 {
-    return !(y[1] - y[0] >= tol && y[2] - y[1] >= tol && y[3] - y[2] >= tol);
+    const double t = fmax(tol, rel * (y[3] - y[0]));
+    return !(y[1] - y[0] >= t && y[2] - y[1] >= t && y[3] - y[2] >= t);
 }
 
 // sum_j W_j J_j for one final tetrahedron (unsorted input) at one frequency.  With a single

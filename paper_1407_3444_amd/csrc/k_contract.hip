@@ -95,8 +95,10 @@ __device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &
 // Every FP64 operand x is split as x = hi + lo with hi = round16(x) and
 // lo = round16((x - hi) * S) / S (S = 2^11 for FP16, whose exponent range would flush
 // small remainders; S = 1 for BF16), and a product is taken as
-// hi*hi + (hi*lo + lo*hi) / S: three MFMAs, the dropped lo*lo term is below the FP32
-// accumulation error.  The complex product is folded into real GEMMs over a doubled
+// hi*hi + (hi*lo + lo*hi) / S: three MFMAs.  hi and lo together carry 2 x 8 significant bits
+// for BF16 and 2 x 11 for FP16, so the dropped lo*lo term and the rounding of lo leave a relative
+// error of about 2^-16 per product for BF16 (well above the FP32 accumulation's 2^-24) and about
+// 2^-22 for FP16.  The complex product is folded into real GEMMs over a doubled
 // reduction axis:  Re M = [Cr Ci] . [Br; Bi],  Im M = [Cr Ci] . [Bi; -Br].
 // ---------------------------------------------------------------------------
 

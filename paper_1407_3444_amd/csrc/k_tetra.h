@@ -1,4 +1,5 @@
-// k_tetra.hip -- the tetrahedron kernel of the chi0 path (K_B).
+// k_tetra.h -- device code of the tetrahedron kernel of the chi0 path (K_B), shared by the
+// translation units that instantiate its kernels (k_tetra_*.hip).
 //
 // One work unit is one (mesh tetrahedron, band pair) of one q.  A workgroup is
 // one 64-lane wave; rounds of 64 consecutive units are dealt to the workgroups
@@ -21,6 +22,8 @@
 //
 // Each workgroup writes its partial sums; the reduce kernel (K_R) adds them in
 // block order.
+#pragma once
+
 #include "chi0_internal.h"
 #include "chi0_math.h"
 
@@ -504,7 +507,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 list[lane].c = c0;
                 list[lane].hs = hs0;
                 list[lane].cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
-                list[lane].flags = (hs0 < kRho * dist ? 1 : 0) | (near_degenerate(y, kDegenerateTol) ? 2 : 0);
+                list[lane].flags = (hs0 < kRho * dist ? 1 : 0) | (near_degenerate(y, M.degen_tol, M.degen_rel) ? 2 : 0);
             }
             __syncthreads();
             if (cluster) {
@@ -665,35 +668,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
                                partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue);
 }
 
-// Fused launch over the (instance, q) items of a batch: workgroup -> item from a table, then the
-// item's own frequency count and precision select the instantiation.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_batch_kernel(const BatchItemDev *__restrict__ items,
-                                                         const int32_t *__restrict__ block_item)
-{
-    // one list buffer for both forms, sized for the larger FP64 record
-    __shared__ __attribute__((aligned(16))) unsigned char lbuf[kCapDyn * sizeof(DynRec<false>)];
-    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
-    static_assert(sizeof(DynRec<true>) <= sizeof(DynRec<false>), "mixed records fit the FP64 buffer");
-    DynRec<false> *list = reinterpret_cast<DynRec<false> *>(lbuf);
-    DynRec<true> *list32 = reinterpret_cast<DynRec<true> *>(lbuf);
-    const BatchItemDev it = items[block_item[blockIdx.x]];
-    const int blk = blockIdx.x - it.kb_begin;
-    double *part = it.partial + (int64_t)blk * it.nw * 2;
-    const int slots = (it.nw + kWave - 1) / kWave;
-    switch (slots * 2 + (it.precision != 0 ? 1 : 0)) {
-#define C0_CASE(S)                                                                                        \
-    case 2 * S:                                                                                           \
-        dynamic_body<S, false, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list, queue);          \
-        break;                                                                                            \
-    case 2 * S + 1:                                                                                       \
-        dynamic_body<S, true, false>(it.M, it.Q, it.nblocks, blk, it.omega, it.nw, part, list32, queue);         \
-        break;
-        C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
-#undef C0_CASE
-    default: break;
-    }
-}
-
 // Static evaluation (w = 0, Re only) of units [u0, u1) by workgroup blk of nblocks: rounds of
 // 64 consecutive units dealt round-robin; each lane evaluates its own final tetrahedra.
 // Returns the workgroup's sum (valid in every lane).
@@ -732,290 +706,5 @@ __device__ __forceinline__ double static_body(const MeshDev &M, const QDev &Q, i
     return acc;
 }
 
-// Three waves per SIMD: the static evaluation fits 168 VGPRs with a few spills outside its loops,
-// and its 12 KiB list leaves LDS for twelve workgroups per CU (12% faster than two waves).
-template <bool LIST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void tetra_static_kernel(MeshDev M, BatchDev B, int nblocks,
-                                                          double *__restrict__ partial)
-{
-    __shared__ StatRec list[kCapStat];
-    const int qi = blockIdx.y;
-    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
-    const double acc = static_body<LIST>(M, B.q[qi], 0, n_units, blockIdx.x, nblocks, list);
-    if (threadIdx.x == 0) partial[(int64_t)qi * nblocks + blockIdx.x] = acc;
-}
-
-// Imaginary part alone (tetrahedron delta weights, for the Kramers-Kronig route): every
-// (final tetrahedron, frequency) pair with the frequency strictly inside the tetrahedron's range
-// of D values is queued and evaluated without logarithms (near_im); outside that range the
-// imaginary part vanishes exactly, so nothing else is evaluated.  Up to 16 slots (1024
-// frequencies) per launch.
-struct ImRec {
-    double y[4];                // D at the corners (sorted ascending after the prep pass)
-    double w[4];                // sign * volume * W
-};
-constexpr int kCapIm = 64;      // final tetrahedra per LDS list
-static_assert(kCapIm >= kMaxRecsPerUnit, "a list must hold a whole unit");
-constexpr int kQCapIm = 64;     // work items queued per lane
-
-template <int NSLOT>
-__device__ __forceinline__ void drain_im(const ImRec *list, uint16_t (*queue)[kWave], int &qn, int lane,
-                                         const double *__restrict__ omega, double *acc)
-{
-    while (__any(qn > 0)) {
-        if (qn > 0) {
-            --qn;
-            const int e = queue[qn][lane];
-            const int r = e >> 5, s = e & 31;
-            double y[4], w[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
-            const double v = near_im(y, w, omega[lane + kWave * s]);
-#pragma unroll
-            for (int ss = 0; ss < NSLOT; ++ss) acc[ss] += (s == ss) ? v : 0.0;
-        }
-    }
-}
-
-template <int NSLOT, bool LIST>
-__global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int nblocks,
-                                                      const double *__restrict__ omega, int nw,
-                                                      double *__restrict__ partial)
-{
-    __shared__ ImRec list[kCapIm];
-    __shared__ uint16_t queue[kQCapIm][kWave];
-    const int qi = blockIdx.y;
-    const QDev Q = B.q[qi];
-    const int lane = threadIdx.x;
-    const int blk = blockIdx.x;
-    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
-    double om[NSLOT], acc[NSLOT];
-    bool live[NSLOT];
-    double wlo = omega[nw - 1], whi = wlo;
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-        const int idx = lane + kWave * s;
-        live[s] = idx < nw;
-        om[s] = omega[live[s] ? idx : nw - 1];
-        acc[s] = 0.0;
-        wlo = fmin(wlo, om[s]);
-        whi = fmax(whi, om[s]);
-    }
-    wlo = wave_min(wlo);
-    whi = wave_max(whi);
-    int qn = 0;
-    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
-        const bool valid = base + lane < n_units;
-        int cnt = 0;
-        if (valid) {
-            Vtx t[4];
-            load_unit<LIST>(M, Q, ux, t);
-            cnt = count_unit(t, M.form);
-        }
-        int start = 0;
-        while (start < kWave) {
-            int next;
-            const int nrec = fill_list<ImRec, kCapIm, LIST>(M, Q, ux, valid, cnt, start, lane, list, next);
-            start = next;
-            if (nrec == 0) continue;
-            __syncthreads();
-            for (int r = lane; r < nrec; r += kWave) {
-                double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
-                double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
-                sort4(y, w);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
-            }
-            __syncthreads();
-            for (int r = 0; r < nrec; ++r) {
-                const double y0 = list[r].y[0], y3 = list[r].y[3];
-                // wave-uniform: the tetrahedron's D range misses every frequency of the launch
-                if (__builtin_amdgcn_readfirstlane(y0 < whi && y3 > wlo ? 1 : 0) == 0) continue;
-#pragma unroll
-                for (int s = 0; s < NSLOT; ++s) {
-                    if (live[s] && y0 < om[s] && om[s] < y3) {
-                        queue[qn][lane] = (uint16_t)((r << 5) | s);
-                        ++qn;
-                    }
-                }
-                if (__any(qn > kQCapIm - NSLOT)) drain_im<NSLOT>(list, queue, qn, lane, omega, acc);
-            }
-            drain_im<NSLOT>(list, queue, qn, lane, omega, acc);
-            __syncthreads();
-        }
-    }
-    double *part = partial + ((int64_t)qi * nblocks + blk) * nw * 2;
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-        const int idx = lane + kWave * s;
-        if (idx < nw) {
-            part[2 * idx] = 0.0;
-            part[2 * idx + 1] = acc[s];
-        }
-    }
-}
-
-// Band-pair resolved static evaluation: workgroup x = p * nblk + j takes the units of pair p
-// (its tetrahedra: consecutive units) as part j of nblk; partial[q][j][pair].
-template <bool LIST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void tetra_static_pairs_kernel(MeshDev M, BatchDev B, int nblk,
-                                                                double *__restrict__ partial)
-{
-    __shared__ StatRec list[kCapStat];
-    const int qi = blockIdx.y;
-    const int npairs = M.nbw * M.nbw;
-    const int p = blockIdx.x / nblk, j = blockIdx.x - p * nblk;
-    const int64_t per_pair = tets_per_pair(M);
-    const double acc = static_body<LIST>(M, B.q[qi], (int64_t)p * per_pair, (int64_t)(p + 1) * per_pair, j, nblk, list);
-    if (threadIdx.x == 0) partial[((int64_t)qi * nblk + j) * npairs + p] = acc;
-}
-
-// Work census (diagnostic, untimed): the dynamic evaluation itself (8 slots, so up to
-// kMaxOmegaPerLaunch frequencies), instantiated with counters: units with a non-empty carved
-// region, final tetrahedra, (final tetrahedron, frequency) evaluations of the near branch, far
-// evaluations (one per tetrahedron and frequency on the per-tetrahedron path, one per list and
-// frequency where a whole list is evaluated as one series) and the series terms they use.
-template <bool MIXED, bool LIST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void census_kernel(
-    MeshDev M, BatchDev B, int nblocks, const double *__restrict__ omega, int nw, double *__restrict__ partial,
-    int count_tets, unsigned long long *__restrict__ counts)
-{
-    __shared__ DynRec<MIXED> list[kCapDyn];
-    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
-    const int qi = blockIdx.y;
-    WorkCount wc = {0, 0, 0, 0, 0};
-    dynamic_body<8, MIXED, LIST, true>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
-                                       partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue, &wc,
-                                       count_tets != 0);
-    if (threadIdx.x == 0) {
-        atomicAdd(&counts[0], wc.units);
-        atomicAdd(&counts[1], wc.tets);
-        atomicAdd(&counts[2], wc.near);
-        atomicAdd(&counts[3], wc.far);
-        atomicAdd(&counts[4], wc.terms);
-    }
-}
-
 }  // namespace
-
-hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
-                                const double *omega, int nw, double *partial, bool mixed, hipStream_t s)
-{
-    if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
-    dim3 grid(nblocks, nq), block(kWave);
-    int slots = (nw + kWave - 1) / kWave;
-    if (mesh.tets) {
-        // list plans: slot counts 1, 2, 4, 8 (a kernel with more slots than frequencies idles the
-        // extra ones)
-        slots = slots <= 1 ? 1 : slots <= 2 ? 2 : slots <= 4 ? 4 : 8;
-        switch (slots * 2 + (mixed ? 1 : 0)) {
-#define C0_LIST(S)                                                                                        \
-    case 2 * S:                                                                                           \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false, true>), grid, block, 0, s, mesh, batch, nblocks, \
-                           omega, nw, partial);                                                           \
-        break;                                                                                            \
-    case 2 * S + 1:                                                                                       \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true, true>), grid, block, 0, s, mesh, batch, nblocks,  \
-                           omega, nw, partial);                                                           \
-        break;
-            C0_LIST(1) C0_LIST(2) C0_LIST(4) C0_LIST(8)
-#undef C0_LIST
-        default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (slots * 2 + (mixed ? 1 : 0)) {
-#define C0_CASE(S)                                                                                        \
-    case 2 * S:                                                                                           \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false, false>), grid, block, 0, s, mesh, batch, nblocks, \
-                           omega, nw, partial);                                                           \
-        break;                                                                                            \
-    case 2 * S + 1:                                                                                       \
-        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true, false>), grid, block, 0, s, mesh, batch, nblocks,  \
-                           omega, nw, partial);                                                           \
-        break;
-        C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
-#undef C0_CASE
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total, hipStream_t s)
-{
-    if (nblocks_total < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tetra_batch_kernel, dim3(nblocks_total), dim3(kWave), 0, s, items, block_item);
-    return hipGetLastError();
-}
-
-hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
-                         int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,
-                         hipStream_t s)
-{
-    if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch || nblocks < 1) return hipErrorInvalidValue;
-    dim3 grid(nblocks, nq), block(kWave);
-    const int ct = first_chunk ? 1 : 0;
-    if (mesh.tets) {
-        if (mixed)
-            hipLaunchKernelGGL((census_kernel<true, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial,
-                               ct, counts);
-        else
-            hipLaunchKernelGGL((census_kernel<false, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
-                               partial, ct, counts);
-    } else {
-        if (mixed)
-            hipLaunchKernelGGL((census_kernel<true, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
-                               partial, ct, counts);
-        else
-            hipLaunchKernelGGL((census_kernel<false, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw,
-                               partial, ct, counts);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_tetra_im(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
-                           int nw, double *partial, hipStream_t s)
-{
-    if (nw < 1 || nw > kMaxOmegaIm || nq < 1 || nq > kMaxQBatch || nblocks < 1) return hipErrorInvalidValue;
-    dim3 grid(nblocks, nq), block(kWave);
-    const bool list = mesh.tets != nullptr;
-    if (nw <= 8 * kWave) {
-        if (list)
-            hipLaunchKernelGGL((tetra_im_kernel<8, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
-        else
-            hipLaunchKernelGGL((tetra_im_kernel<8, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
-    } else {
-        if (list)
-            hipLaunchKernelGGL((tetra_im_kernel<16, true>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
-        else
-            hipLaunchKernelGGL((tetra_im_kernel<16, false>), grid, block, 0, s, mesh, batch, nblocks, omega, nw, partial);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch, int nq, int nblk, double *partial,
-                                     hipStream_t s)
-{
-    if (nq < 1 || nq > kMaxQBatch || nblk < 1) return hipErrorInvalidValue;
-    dim3 grid(nblk * mesh.nbw * mesh.nbw, nq), block(kWave);
-    if (mesh.tets)
-        hipLaunchKernelGGL(tetra_static_pairs_kernel<true>, grid, block, 0, s, mesh, batch, nblk, partial);
-    else
-        hipLaunchKernelGGL(tetra_static_pairs_kernel<false>, grid, block, 0, s, mesh, batch, nblk, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,
-                               hipStream_t s)
-{
-    if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
-    dim3 grid(nblocks, nq), block(kWave);
-    if (mesh.tets)
-        hipLaunchKernelGGL(tetra_static_kernel<true>, grid, block, 0, s, mesh, batch, nblocks, partial);
-    else
-        hipLaunchKernelGGL(tetra_static_kernel<false>, grid, block, 0, s, mesh, batch, nblocks, partial);
-    return hipGetLastError();
-}
-
 }  // namespace chi0

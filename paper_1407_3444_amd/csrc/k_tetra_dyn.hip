@@ -1,0 +1,31 @@
+// k_tetra_dyn.hip -- the dynamic tetrahedron kernel (K_B) instantiated for mesh plans, and its
+// launcher (list plans are instantiated in k_tetra_list.hip).
+#include "k_tetra.h"
+
+namespace chi0 {
+
+hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
+                                const double *omega, int nw, double *partial, bool mixed, hipStream_t s)
+{
+    if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nq), block(kWave);
+    int slots = (nw + kWave - 1) / kWave;
+    if (mesh.tets) return launch_tetra_dynamic_list(mesh, batch, nq, nblocks, omega, nw, partial, mixed, s);
+    switch (slots * 2 + (mixed ? 1 : 0)) {
+#define C0_CASE(S)                                                                                        \
+    case 2 * S:                                                                                           \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, false, false>), grid, block, 0, s, mesh, batch, nblocks, \
+                           omega, nw, partial);                                                           \
+        break;                                                                                            \
+    case 2 * S + 1:                                                                                       \
+        hipLaunchKernelGGL((tetra_dynamic_kernel<S, true, false>), grid, block, 0, s, mesh, batch, nblocks,  \
+                           omega, nw, partial);                                                           \
+        break;
+        C0_CASE(1) C0_CASE(2) C0_CASE(3) C0_CASE(4) C0_CASE(5) C0_CASE(6) C0_CASE(7) C0_CASE(8)
+#undef C0_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace chi0

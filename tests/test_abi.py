@@ -244,3 +244,121 @@ def test_list_plan_validates_on_the_host():
     assert make(volume=0.0) == -1
     assert make(volume=float("nan")) == -1
     assert so.chi0_plan_list(ctypes.byref(h), ctypes.byref(d), None, FAKE, None, None) == -1
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("batch_hint", 17, -1), ("batch_hint", -1, -1), ("skip_input_scan", 2, -1),
+    ("degen_tol_ev", float("nan"), -3), ("degen_rel_tol", float("inf"), -3),
+    ("degen_tol_ev", -1e-6, -1), ("degen_rel_tol", -0.1, -1),
+])
+def test_plan_rejects_bad_new_descriptor_fields(field, value, status):
+    d = _desc()
+    setattr(d, field, value)
+    st, h = _plan(d)
+    assert st == status and not h.value
+
+
+def test_plan_rejects_nonzero_reserved():
+    d = _desc()
+    d.reserved[2] = 1
+    assert _plan(d)[0] == -1
+
+
+def test_q_from_fraction_is_checked_on_the_host():
+    so = lib.load_library()
+    st, h = _plan(_desc(nk=(4, 4, 8)))
+    assert st == 0
+    try:
+        q = (lib._Q * 1)()
+        q[0].explicit_kq = 2
+        ws, out = ctypes.c_void_p(0x3000), ctypes.c_void_p(0x2000)
+        q[0].q_frac[0], q[0].q_frac[1], q[0].q_frac[2] = 0.3, 0.0, 0.0     # 0.3 * 4 is not an integer
+        assert so.chi0_static(h, 1, q, ws, 1 << 40, out) == -4
+        assert b"not a vector of the mesh" in so.chi0_last_error(h)
+        q[0].q_frac[0] = float("nan")
+        assert so.chi0_static(h, 1, q, ws, 1 << 40, out) == -3
+        # commensurate (and periodic images) pass the q check and stop at the workspace check
+        for frac in ((0.25, -0.5, 0.125), (1.75, 3.0, -0.875)):
+            q[0].q_frac[0], q[0].q_frac[1], q[0].q_frac[2] = frac
+            assert so.chi0_static(h, 1, q, ws, 16, out) == -5
+        q[0].explicit_kq = 3
+        assert so.chi0_static(h, 1, q, ws, 1 << 40, out) == -1
+        assert so.chi0_status_string(-4) == b"q not commensurate with the mesh"
+        assert so.chi0_status_string(-8) == b"eigenvectors not normalised"
+    finally:
+        so.chi0_destroy(h)
+    assert so.chi0_sync(None) == -1
+
+
+def test_batch_hint_bounds_the_workspace():
+    so = lib.load_library()
+    sizes = []
+    for hint in (0, 16, 4, 1):
+        d = _desc(nk=(16, 16, 16), n_bands=8, n_orb=8)
+        d.batch_hint = hint
+        st, h = _plan(d)
+        assert st == 0
+        s = ctypes.c_size_t()
+        assert so.chi0_workspace_size(h, 64, 512, ctypes.byref(s)) == 0
+        sizes.append(s.value)
+        so.chi0_destroy(h)
+    w_per_q = 8 * 8 * 8 * 16 ** 3
+    assert sizes[0] == sizes[1] > sizes[2] > sizes[3]
+    assert sizes[1] - sizes[2] >= 12 * w_per_q and sizes[2] - sizes[3] >= 3 * w_per_q
+
+
+def test_batch_rejects_plane_wave_bases():
+    a, qa = _instance(nk=(4, 4, 4), n_bands=8, n_orb=128)
+    assert _batch_size([a])[0] == -7
+    b, qb = _instance(nk=(4, 4, 4), n_bands=8, n_orb=64)
+    assert _batch_size([b])[0] == 0
+
+
+class _FakeDev:
+    """Stands in for a device tensor in the binding's host-side checks (never dereferenced)."""
+
+    def __init__(self, shape, dtype):
+        import torch
+        self.shape = tuple(shape)
+        self.dtype = getattr(torch, dtype)
+        self.is_cuda = True
+
+    def dim(self):
+        return len(self.shape)
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_checks_shapes_before_passing_pointers():
+    eps = _FakeDev((10, 64), "float64")
+    ck = _FakeDev((64, 10, 10), "complex128")
+    lib._check_band_arrays(eps, ck, 64, False)
+    with pytest.raises(ValueError, match="eps_k"):
+        lib._check_band_arrays(_FakeDev((10, 63), "float64"), ck, 64, False)
+    with pytest.raises(ValueError, match="c_k"):
+        lib._check_band_arrays(eps, _FakeDev((64, 10, 9), "complex128"), 64, False)
+    with pytest.raises(ValueError, match="expected torch.complex128"):
+        lib._check_band_arrays(eps, _FakeDev((64, 10, 10), "float64"), 64, False)
+    lib._check_band_arrays(eps, None, 64, True)
+    q = lib._Q()
+    lib._q_struct(lib.Q(eps_kq=_FakeDev((10, 64), "float64"), c_kq=_FakeDev((64, 10, 10), "complex128")), q,
+                  eps, ck, False)
+    assert q.explicit_kq == 1
+    with pytest.raises(ValueError, match="eps_kq"):
+        lib._q_struct(lib.Q(eps_kq=_FakeDev((10, 32), "float64"), c_kq=ck), lib._Q(), eps, ck, False)
+    with pytest.raises(ValueError, match="c_kq"):
+        lib._q_struct(lib.Q(eps_kq=eps, c_kq=_FakeDev((32, 10, 10), "complex128")), lib._Q(), eps, ck, False)
+    with pytest.raises(ValueError, match="c_kq is required"):
+        lib._q_struct(lib.Q(eps_kq=eps), lib._Q(), eps, ck, False)
+    qf = lib._Q()
+    lib._q_struct(lib.Q(q_frac=(0.25, 0.0, 0.5), from_frac=True), qf)
+    assert qf.explicit_kq == 2 and qf.q_frac[2] == 0.5
+    lib._out_f64(_FakeDev((3, 8, 2), "float64"), (3, 8, 2), "out")
+    with pytest.raises(ValueError, match="out"):
+        lib._out_f64(_FakeDev((3, 7, 2), "float64"), (3, 8, 2), "out")
+    with pytest.raises(ValueError, match="out"):
+        lib._out_f64(_FakeDev((3,), "float32"), (3,), "out")

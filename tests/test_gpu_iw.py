@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import synth
+from metrics import max_err
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +30,7 @@ def _say(*a):
 
 
 def _relerr(got, ref):
+    """Normwise difference of two GPU results (consistency of two launch schedules)."""
     return np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
 
 
@@ -71,7 +73,7 @@ def test_wedge_point_group_loop_matches_oracle(kind, n):
         plan, qs = _plan_and_qs(tets, vol, e, c, ents, mu=mu, cma=cma, form=form)
         got = plan.dynamic_group(qs, 48, _dev(omega)).cpu().numpy()[0]
         ref = oracle.chi0_iw(e, c, ents, tets, vol, omega, mu=mu, cma=cma, form=form)
-        err = _relerr(got, ref)
+        err = max_err(got, ref)
         _say("form", form, "dynamic rel err", err)
         assert err <= TOL, (form, err)
         st = plan.static_group(qs, 48).cpu().numpy()[0]

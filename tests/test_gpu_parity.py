@@ -1,6 +1,8 @@
 """GPU parity: libchi0 (HIP, gfx950) against the CPU FP64 oracle on the same seeded inputs.
 
-Bar for the all-FP64 path: per q, max_w |chi_gpu - chi_oracle| / max_w |chi_oracle| <= 1e-10.
+Bar for the all-FP64 path: every result within 1e-10 of the oracle's, relative to the result
+(per q and frequency, |got - ref| / max(|ref|, 1e-3 max_w |ref|), see tests/metrics.py); 1e-5 for
+the mixed-precision forms.
 """
 import os
 import sys
@@ -10,6 +12,7 @@ import pytest
 
 import oracle
 import synth
+from metrics import max_err, mean_err
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +47,8 @@ def _plan(wl, **kw):
 
 
 def _relerr(got, ref):
-    return np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+    """Largest per-result error (tests/metrics.py)."""
+    return max_err(got, ref)
 
 
 def _say(*a):
@@ -230,7 +234,7 @@ def test_dynamic_mixed_precision_error(precision):
     for i in range(len(wl.qs)):
         ref = oracle.chi0(wl, i)
         err = _relerr(got[i], ref)
-        _say(f"q {i}: max rel err {err:.2e}")
+        _say(f"q {i}: per-result rel err max {err:.2e}, mean {mean_err(got[i], ref):.2e}")
         assert err <= 1e-5
 
 
@@ -254,14 +258,15 @@ def test_dynamic_mixed_precision_degenerate_model():
     for i in range(len(wl.qs)):
         ref = oracle.chi0(wl, i, omega=om)
         err = _relerr(got[i], ref)
-        _say(f"q {i}: max rel err {err:.2e}")
+        _say(f"q {i}: per-result rel err max {err:.2e}, mean {mean_err(got[i], ref):.2e}")
         assert err <= 1e-5
 
 
-@pytest.mark.parametrize("n_keep", [9, 5])
+@pytest.mark.parametrize("n_keep", [9, 7, 5])
 def test_full_size_bcc_band_windows_sampled(n_keep):
     """The 9-orbital bcc model on the full 48^3 mesh (663,552 tetrahedra), one q of the (010)
-    path, 512 w, with the 9-band sum and a 5-band truncation; the oracle checks 2 frequencies."""
+    path, 512 w, with the 9-band sum and the 7- and 5-band truncations (Sec. III); the oracle
+    checks 2 frequencies."""
     torch = _torch()
     wl = synth.make_workload("bcc_dynamic", q_subset=[20], n_keep=n_keep, workers=8)
     plan, qs = _plan(wl)
@@ -287,9 +292,8 @@ def test_static_band_pairs(nk, window):
     tot = plan.static(qs).cpu().numpy()
     for i in range(len(wl.qs)):
         ref = oracle.chi0_pairs(wl, i)[:, :, 0].real
-        scale = np.max(np.abs(ref))
-        err = np.max(np.abs(got[i] - ref)) / scale
-        _say(f"q {i}: max pair error / max pair {err:.2e}")
+        err = max_err(got[i].ravel(), ref.ravel())        # per pair, floor 1e-3 of the largest pair
+        _say(f"q {i}: max per-pair error {err:.2e}")
         assert err <= TOL
         assert abs(got[i].sum() - tot[i]) <= 1e-12 * abs(tot[i])
 
@@ -314,8 +318,8 @@ def test_dynamic_kk_route(n_spec):
     for i in range(len(wl.qs)):
         ref = oracle.chi0_kk(wl, i, wl.omega, n_spec, dmin, dmax)
         exact = oracle.chi0(wl, i)
-        e_im = np.max(np.abs(got[i].imag - exact.imag)) / np.max(np.abs(exact))
-        e_re = np.max(np.abs(got[i].real - ref.real)) / np.max(np.abs(ref.real))
+        e_im = max_err(got[i].imag, exact.imag)
+        e_re = max_err(got[i].real, ref.real)
         kk_vs_exact = np.max(np.abs(got[i].real - exact.real)) / np.max(np.abs(exact.real))
         _say(f"q {i}: Im err {e_im:.2e}, Re vs oracle KK {e_re:.2e}, KK Re vs analytic {kk_vs_exact:.2e}")
         assert e_im <= TOL and e_re <= TOL
@@ -422,25 +426,33 @@ def test_census_counts_the_evaluation():
 
 
 def test_nonfinite_frequency_only_affects_itself():
-    """A NaN or infinite frequency is not rejected (device arrays are not scanned): a NaN gives NaN
-    at its own frequency and leaves every other one bit for bit unchanged; an infinite frequency
-    (whose own value is not meaningful) widens the frequency interval the series are cut for, and
-    the other frequencies keep the FP64 bar."""
+    """A NaN or infinite frequency does not stop the call: a NaN gives NaN at its own frequency and
+    leaves every other one bit for bit unchanged; an infinite frequency (whose own value is not
+    meaningful) widens the frequency interval the series are cut for, and the other frequencies
+    keep the FP64 bar.  The input scan reports both at the next synchronisation."""
     torch = _torch()
+    import paper_1407_3444_amd as lib
     wl = synth.make_workload("tetra_dynamic", nk=(6, 6, 2), nq=8, q_subset=[3], nw=40)
     plan, qs = _plan(wl)
     om = wl.omega.copy()
     ref = plan.dynamic(qs, torch.from_numpy(om).cuda()).cpu().numpy()[0]
+    plan.sync()
     keep = np.ones(len(om), bool)
     keep[7] = False
     bad = om.copy()
     bad[7] = np.nan
     got = plan.dynamic(qs, torch.from_numpy(bad).cuda()).cpu().numpy()[0]
+    with pytest.raises(lib.Chi0Error) as e:
+        plan.sync()
+    assert e.value.status == -3 and "frequencies" in str(e.value)
     assert np.array_equal(got[keep], ref[keep])
     assert np.isnan(got[7].real)
     bad[7] = np.inf
     got = plan.dynamic(qs, torch.from_numpy(bad).cuda()).cpu().numpy()[0]
-    assert _relerr(got[keep], ref[keep]) <= TOL
+    with pytest.raises(lib.Chi0Error) as e:
+        plan.sync()
+    assert e.value.status == -3
+    assert np.max(np.abs(got[keep] - ref[keep])) <= TOL * np.max(np.abs(ref[keep]))
 
 
 def test_frequencies_on_corner_values_and_widest_window():
@@ -466,3 +478,56 @@ def test_frequencies_on_corner_values_and_widest_window():
     got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()[0]
     ref = oracle.chi0(wl, 0)
     assert _relerr(got, ref) <= TOL
+
+
+def _lindhard_static(q, kf):
+    """Free-electron static Lindhard function (m = hbar = 1, g_s = 2, per unit volume)."""
+    x = q / (2 * kf)
+    return -kf / np.pi ** 2 * (0.5 + (1 - x * x) / (4 * x) * np.log(abs((1 + x) / (1 - x))))
+
+
+def test_free_electron_gamma_r_static_against_oracle_and_lindhard():
+    """The free-electron variant of the single-band configuration: eps = k^2/2 on the 16^3 index
+    mesh spanning [-pi, pi)^3, k_F = pi/2, the Eq. (1) form (region e < mu < e' only, so the
+    Fermi sphere at k+q never needs to fit the box), explicit k+q data at the 8 points
+    q_j = (j/16)(1,1,1) of Gamma-R (reciprocal lattice 2 pi).  Every value within 1e-10 of the
+    oracle; both within the linear-tetrahedron discretisation error of the Lindhard closed form
+    (the oracle's own pin shows it falling as h^2)."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    nk = (16, 16, 16)
+    kf = np.pi / 2
+    e = synth.free_electron_eps(nk)
+    dev = torch.device("cuda:0")
+    plan = lib.Chi0Plan(nk, torch.from_numpy(e).to(dev), None, mu=kf ** 2 / 2, cma=True, form=1)
+    qs, qcart = [], []
+    for j in range(1, 9):
+        qc = np.full(3, j / 16 * 2 * np.pi)
+        qcart.append(qc)
+        qs.append(lib.Q(eps_kq=torch.from_numpy(synth.free_electron_eps(nk, qc)).to(dev)))
+    _say("free electrons 16^3, Gamma-R, form 1")
+    got = plan.static(qs).cpu().numpy()
+    for j, qc in enumerate(qcart):
+        ref = oracle.chi0_raw(nk, e, None, [0.0], eps_kq=synth.free_electron_eps(nk, qc), mu=kf ** 2 / 2,
+                              cma=True, form=1)[0].real
+        lind = _lindhard_static(np.linalg.norm(qc), kf)
+        _say(f"q {j + 1}: gpu {got[j]:.12e} oracle {ref:.12e} Lindhard {lind:.6e}")
+        assert abs(got[j] - ref) <= TOL * abs(ref), (j, got[j], ref)
+        # 16^3 discretisation error: 1.5% near q = 0, up to 6% past 2 k_F (the kink of the Lindhard
+        # function); the oracle pin shows it falling as h^2 on finer meshes
+        assert abs(got[j] - lind) <= 0.07 * abs(lind), (j, got[j], lind)
+
+
+def test_full_size_dynamic_q_in_the_last_launch():
+    """The benchmark's configuration with 20 q: two launch sequences (16 + 4 q); a q of the second
+    one is checked against the oracle at 3 frequencies, a q of the first at 1."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", q_subset=list(range(44, 64)), workers=8)
+    plan, qs = _plan(wl)
+    _say("full-size dynamic 64x64x8, 20 q x 512 w (launches of 16 + 4 q)")
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
+    for i, sample in ((18, [3, 257, 508]), (5, [130])):
+        ref = oracle.chi0(wl, i, omega=wl.omega[sample])
+        err = _relerr(got[i][sample], ref)
+        _say(f"q index {44 + i}: max per-result error {err:.2e}")
+        assert err <= TOL, (i, got[i][sample], ref)
