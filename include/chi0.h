@@ -159,6 +159,18 @@ chi0_status chi0_dynamic(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t
                          const double *omega, void *workspace, size_t workspace_bytes,
                          double *chi);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): chi0_dynamic with its workspace in a fixed device array
+ * of the library, 128 MiB per device (held from the first call on a device until the process
+ * ends), instead of a caller buffer.  Arguments and results as for chi0_dynamic.  Each launch
+ * sequence takes as many q-points as the array holds (at most the plan's batch_hint); a plan whose
+ * workspace for a single q exceeds 128 MiB is rejected with CHI0_E_WORKSPACE.  Allocates nothing
+ * (no device or pinned memory, no profile events even while profiling is enabled).  Every call on
+ * a device shares that device's array: calls that overlap on one device (any plans, any streams)
+ * race, so they must be serialised by the caller. */
+chi0_status chi0_dynamic_noalloc(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
+                                 const double *omega, double *chi);
+
 /* The Kramers-Kronig route (Sec. II: one usually computes Im chi0 only and obtains Re chi0 from it
  * by the Kramers-Kronig relation, provided the frequencies cover the whole spectrum).
  * Im chi0 is computed exactly (tetrahedron delta weights, no logarithms) at the requested

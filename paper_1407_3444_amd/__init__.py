@@ -22,6 +22,7 @@ __all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library"
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
 EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
+                    "chi0_dynamic_noalloc",
                     "chi0_kk_workspace_size", "chi0_dynamic_kk", "chi0_plan_list", "chi0_static_group",
                     "chi0_dynamic_group", "chi0_iw_cubic",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_dynamic_kk.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, i32, ctypes.c_double, ctypes.c_double,
                                     vp, sz, vp]
     lib.chi0_dynamic.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
+    lib.chi0_dynamic_noalloc.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp]
     lib.chi0_matrix_elements.argtypes = [vp, ctypes.POINTER(_Q), vp]
     lib.chi0_profile_enable.argtypes = [vp, i32]
     lib.chi0_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
@@ -125,6 +127,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_batch_last_error.argtypes = [vp]
     lib.chi0_batch_last_error.restype = ctypes.c_char_p
     for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
+                 "chi0_dynamic_noalloc",
                  "chi0_kk_workspace_size", "chi0_dynamic_kk",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                  "chi0_sync", "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
@@ -364,6 +367,19 @@ class Chi0Plan:
         chi = _out_f64(out if out is not None else self._new((nq, nw, 2)), (nq, nw, 2), "out")
         self._check(self._lib.chi0_dynamic(self._h, nq, arr, nw, op, wp, wn, ctypes.c_void_p(chi.data_ptr())),
                     "chi0_dynamic")
+        return torch.view_as_complex(chi)
+
+    def dynamic_noalloc(self, qs: Sequence[Q], omega, out):
+        """chi0_dynamic_noalloc: as dynamic() with the library's fixed device scratch as workspace; the
+        output tensor must be supplied (float64 [nq, nw, 2] or complex128 [nq, nw]), so nothing is
+        allocated on this path."""
+        import torch
+        nq = len(qs)
+        nw, op = self._omega(omega)
+        arr = self._qarray(qs)
+        chi = _out_f64(out, (nq, nw, 2), "out")
+        self._check(self._lib.chi0_dynamic_noalloc(self._h, nq, arr, nw, op, ctypes.c_void_p(chi.data_ptr())),
+                    "chi0_dynamic_noalloc")
         return torch.view_as_complex(chi)
 
     def static_group(self, qs: Sequence[Q], n_group: int, workspace=None, out=None):

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchi0.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build", "libchi0")
 SOURCES = ["k_tetra_dyn.hip", "k_tetra_list.hip", "k_tetra_batch.hip", "k_tetra_misc.hip", "k_contract.hip",
-           "k_reduce.hip", "k_kk.hip", "k_check.hip", "chi0_api.cpp", "chi0_batch.cpp", "chi0_iw.cpp"]
+           "k_reduce.hip", "k_kk.hip", "k_check.hip", "chi0_api.cpp", "chi0_batch.cpp", "chi0_iw.cpp",
+           "chi0_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -157,19 +157,20 @@ chi0_status enqueue_scan(chi0_plan_s *p, int nq, const chi0_q *qs, const double 
     if (e == hipSuccess) e = launch_scan_finite(M.eps_k, (int64_t)M.nb * M.nk, kScanEps, flag, p->stream);
     if (e == hipSuccess && !M.cma)
         e = launch_scan_eigvec(M.c_k, M.nk, M.no, M.nb, kScanEig, kScanNorm, tol, flag, p->stream);
-    std::vector<const void *> seen;
+    // each distinct explicit array once (an array repeated in several entries, as in a group
+    // call, is scanned at its first entry; no host allocation on this path)
+    auto first_use = [&](int i, bool eps) {
+        const void *a = eps ? (const void *)qs[i].eps_kq : (const void *)qs[i].c_kq;
+        for (int j = 0; j < i; ++j)
+            if (qs[j].explicit_kq == 1 && (eps ? (const void *)qs[j].eps_kq : (const void *)qs[j].c_kq) == a)
+                return false;
+        return true;
+    };
     for (int i = 0; i < nq && e == hipSuccess; ++i) {
         if (qs[i].explicit_kq != 1) continue;
-        const void *key = qs[i].eps_kq;
-        if (std::find(seen.begin(), seen.end(), key) == seen.end()) {
-            seen.push_back(key);
-            e = launch_scan_finite(qs[i].eps_kq, (int64_t)M.nb * M.nk, kScanEps, flag, p->stream);
-        }
-        if (e == hipSuccess && !M.cma && qs[i].c_kq &&
-            std::find(seen.begin(), seen.end(), (const void *)qs[i].c_kq) == seen.end()) {
-            seen.push_back(qs[i].c_kq);
+        if (first_use(i, true)) e = launch_scan_finite(qs[i].eps_kq, (int64_t)M.nb * M.nk, kScanEps, flag, p->stream);
+        if (e == hipSuccess && !M.cma && qs[i].c_kq && first_use(i, false))
             e = launch_scan_eigvec(qs[i].c_kq, M.nk, M.no, M.nb, kScanEig, kScanNorm, tol, flag, p->stream);
-        }
     }
     if (e == hipSuccess && omega) e = launch_scan_finite(omega, nw, kScanOmega, flag, p->stream);
     if (e == hipSuccess)
@@ -211,10 +212,11 @@ struct Layout {
     int qbatch;
 };
 
-Layout layout(const chi0_plan_s *p, int nq, int nvals)
+// qcap > 0 caps the q-points per launch sequence below the plan's own (the no-allocation call)
+Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0)
 {
     Layout L;
-    L.qbatch = std::min(nq, p->qbatch);
+    L.qbatch = std::min(nq, qcap > 0 ? std::min(qcap, p->qbatch) : p->qbatch);
     L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
     // the partial sums of a dynamic or static call, or of a pair-resolved static call
     const size_t npairs = (size_t)p->mesh.nbw * p->mesh.nbw;
@@ -305,10 +307,11 @@ void fill_batch(const chi0_plan_s *p, const chi0_q *qs, int q0, int nqb, void *w
 }
 
 // Run one launch, bracketed by events when profiling.
+// (no_alloc: the no-allocation call records no profile events, whose creation allocates)
 template <class F>
-hipError_t timed(chi0_plan_s *p, int kind, F &&launch)
+hipError_t timed(chi0_plan_s *p, int kind, F &&launch, bool no_alloc = false)
 {
-    if (!p->profiling) return launch();
+    if (!p->profiling || no_alloc) return launch();
     TimedLaunch t;
     t.kind = kind;
     hipError_t e = hipEventCreate(&t.start);
@@ -693,20 +696,23 @@ chi0_status chi0_static_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, void 
     return CHI0_OK;
 }
 
-chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega, void *ws,
-                         size_t ws_bytes, double *chi)
+}  // extern "C"
+
+namespace {
+
+// The dynamic call on a given workspace, at most qcap q-points per launch sequence (0: the
+// plan's own); no_alloc: no profile events.
+chi0_status dynamic_run(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega, void *ws,
+                        size_t ws_bytes, double *chi, int qcap, bool no_alloc)
 {
-    if (!p) return CHI0_E_INVALID_ARG;
     chi0_status st = begin_call(p);
     if (st) return st;
     st = check_qs(p, nq, qs);
     if (st) return st;
     if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
-    const Layout L = layout(p, nq, 2 * nwc_max);
-    size_t need = 0;
-    chi0_workspace_size(p, nq, nw, &need);
-    if (!ws || ws_bytes < need || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    const Layout L = layout(p, nq, 2 * nwc_max, qcap);
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
@@ -717,23 +723,56 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
         if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); }, no_alloc)) !=
+                hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
             if ((e = timed(p, 1, [&] {
                      return launch_tetra_dynamic(p->mesh, B, nqb, nblk, omega + w0, nwc, partial, p->d.precision != 0,
                                                  p->stream);
-                 })) != hipSuccess)
+                 }, no_alloc)) != hipSuccess)
                 return device_fail(p, e, "tetrahedron kernel");
             if ((e = timed(p, 2, [&] {
                      return launch_reduce(partial, nqb, nblk, 2 * nwc, scale, chi + ((int64_t)q0 * nw + w0) * 2,
                                           (int64_t)nw * 2, p->stream);
-                 })) != hipSuccess)
+                 }, no_alloc)) != hipSuccess)
                 return device_fail(p, e, "reduce kernel");
         }
     }
     return CHI0_OK;
+}
+
+}  // namespace
+
+namespace chi0 {
+
+chi0_status dynamic_scratch(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega,
+                            void *scratch, size_t scratch_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || nw < 1) return fail(p, CHI0_E_INVALID_ARG, "nq and nw must be >= 1");
+    const int nvals = 2 * std::min(nw, kMaxOmegaPerLaunch);
+    int qcap = p->qbatch;
+    while (qcap > 1 && layout(p, nq, nvals, qcap).total > scratch_bytes) --qcap;
+    if (layout(p, nq, nvals, qcap).total > scratch_bytes)
+        return fail(p, CHI0_E_WORKSPACE, "the no-allocation call's fixed scratch cannot hold the workspace of one q of "
+                                         "this plan (use chi0_dynamic with a caller workspace)");
+    return dynamic_run(p, nq, qs, nw, omega, scratch, scratch_bytes, chi, qcap, true);
+}
+
+chi0_status plan_device_error(chi0_plan_t p, hipError_t e, const char *where) { return device_fail(p, e, where); }
+
+}  // namespace chi0
+
+extern "C" {
+
+chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega, void *ws,
+                         size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    // the workspace chi0_workspace_size reports is exactly the layout of the plan's own batch
+    return dynamic_run(p, nq, qs, nw, omega, ws, ws_bytes, chi, 0, false);
 }
 
 chi0_status chi0_kk_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, int32_t n_spec, size_t *bytes)
