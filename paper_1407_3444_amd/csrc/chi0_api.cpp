@@ -225,7 +225,7 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0)
     L.w_off = 0;
     L.part_off = L.w_bytes_per_q * L.qbatch;
     L.count_off = L.part_off + L.part_bytes_per_q * L.qbatch;
-    L.flag_off = L.count_off + 128;       // census counters (40 bytes), then the scan verdict
+    L.flag_off = L.count_off + 128;       // census counters (48 bytes), then the scan verdict
     L.total = L.count_off + kAlign;
     return L;
 }
@@ -598,7 +598,7 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
     auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
-    hipError_t e = hipMemsetAsync(dc, 0, 5 * sizeof(unsigned long long), p->stream);
+    hipError_t e = hipMemsetAsync(dc, 0, 6 * sizeof(unsigned long long), p->stream);
     if (e != hipSuccess) return device_fail(p, e, "census clear");
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
@@ -612,11 +612,11 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
                 return device_fail(p, e, "census kernel");
         }
     }
-    unsigned long long h[5];
+    unsigned long long h[6];
     if ((e = hipMemcpyAsync(h, dc, sizeof h, hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(p->stream)) != hipSuccess)
         return device_fail(p, e, "census copy");
-    for (int i = 0; i < 5; ++i) counts[i] = h[i];
+    for (int i = 0; i < 6; ++i) counts[i] = h[i];
     return CHI0_OK;
 }
 

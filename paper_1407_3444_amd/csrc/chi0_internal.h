@@ -107,10 +107,11 @@ hipError_t launch_tetra_dynamic_list(const MeshDev &mesh, const BatchDev &batch,
                                      const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 
 // Census of the work of a dynamic call (nw <= kMaxOmegaPerLaunch), by the dynamic evaluation
-// itself with counters (it also writes the call's partial sums): counts[0..4] += active units,
+// itself with counters (it also writes the call's partial sums): counts[0..5] += active units,
 // final tetrahedra, near-branch evaluations, far-branch evaluations (per final tetrahedron and
-// frequency, or per list of final tetrahedra and frequency where a list is one series), and the
-// series terms of the far evaluations (FP32 series when mixed).  Units and final tetrahedra are
+// frequency, or per list of final tetrahedra and frequency where a list is one series), the
+// series terms of the far evaluations (FP32 series when mixed), and the near evaluations repeated
+// in full (FP64 form: an entry's nodes cluster).  Units and final tetrahedra are
 // counted only when first_chunk is set (the first frequency chunk of a call).
 hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
                          int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,

@@ -340,6 +340,20 @@ C0_HD float rcp(float d)
 #ifndef CHI0_THETA_ENTRY32
 #define CHI0_THETA_ENTRY32 0.3
 #endif
+#ifndef CHI0_DEFER_PAIR_SERIES
+#define CHI0_DEFER_PAIR_SERIES 1
+#endif
+// 2-node entries in FP64: the series is selected below the smaller ratio kThetaPair, with
+// kPairTerms terms; between kThetaPair and kThetaEntry the recursion loses at most a factor
+// 1/kThetaPair of relative accuracy on the entry.
+#ifndef CHI0_THETA_PAIR
+#define CHI0_THETA_PAIR 0.02
+#endif
+#ifndef CHI0_PAIR_TERMS
+#define CHI0_PAIR_TERMS 8
+#endif
+constexpr double kThetaPair = CHI0_THETA_PAIR;
+constexpr int kPairTerms = CHI0_PAIR_TERMS;
 constexpr int kEntryTerms = CHI0_ENTRY_TERMS;
 constexpr int kEntryTerms32 = CHI0_ENTRY_TERMS32;
 constexpr double kThetaEntry32 = CHI0_THETA_ENTRY32;
@@ -348,10 +362,14 @@ template <class T> struct NearParams;
 template <> struct NearParams<double> {
     static constexpr int terms = kEntryTerms;
     static constexpr double theta = kThetaEntry;
+    static constexpr int pair_terms = kPairTerms;
+    static constexpr double theta_pair = kThetaPair;
 };
 template <> struct NearParams<float> {
     static constexpr int terms = kEntryTerms32;
     static constexpr double theta = kThetaEntry32;
+    static constexpr int pair_terms = kEntryTerms32;
+    static constexpr double theta_pair = kThetaEntry32;
 };
 
 C0_HD double entry_coef(int n) { return 6.0 / ((double)n * (n - 1) * (n - 2) * (n - 3)); }
@@ -393,7 +411,7 @@ C0_HD void taylor_pair(T yo_ye, T we, T wo, T u, cx<T> L, cx<T> &val, cx<T> &tan
     // m >= 3: real coefficients 6/(n(n-1)(n-2)(n-3)) u^2, n = m + 1
     T zprev = z * z, sv = T(0), st = T(0);
 #pragma unroll
-    for (int m = 3; m < NearParams<T>::terms; ++m) {
+    for (int m = 3; m < NearParams<T>::pair_terms; ++m) {
         const T zm = zprev * z;
         const T cf = T(entry_coef(m + 1));
         sv = fmaT(cf, zm, sv);
@@ -444,8 +462,8 @@ C0_HD void taylor_triple(T y1_ye, T y2_ye, T we, T w1, T w2, T u, cx<T> L, cx<T>
 // One Newton entry over nodes y[0..P] (P = 1, 2) from its two children A = [y_1..y_P] and
 // B = [y_0..y_{P-1}], or, when its nodes cluster within theta of their distance to w, from the
 // Taylor series about its end node farther from w.  y: FP64 node values; u: w - y in T.
-// SERIES = false (3-node entries only): the series is not evaluated; *need is set when it would
-// have been selected, and the entry then holds the (inaccurate) recursion value.
+// SERIES = false: the series is not evaluated; *need is set when it would have been selected, and
+// the entry then holds the (inaccurate) recursion value.
 template <int P, class T, bool SERIES = true>
 C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L, cx<T> A, cx<T> dA, cx<T> B,
                         cx<T> dB, cx<T> &V, cx<T> &Tg, bool *need = nullptr)
@@ -459,7 +477,7 @@ C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L,
     const T d0 = absT(u[0]), dP = absT(u[P]);
     const bool first = d0 >= dP;
     const T far = first ? d0 : dP;
-    const bool use_series = span <= T(NearParams<T>::theta) * far;
+    const bool use_series = span <= T(P == 1 ? NearParams<T>::theta_pair : NearParams<T>::theta) * far;
     if (!SERIES) {
         *need = *need || use_series;
         V = E;
@@ -489,9 +507,10 @@ C0_HD void newton_entry(const double *y, const T *w, const T *u, const cx<T> *L,
 // h is taken with Log(u) - log(s), s the span of the nodes: the dropped part log(s) u^3 is a
 // cubic, whose third divided difference is a constant, so the W-derivative is unchanged while
 // the logarithms stay O(1) (no cancellation of a large common log(s) between the leaves).
-// TRIPLE = false: the two 3-node entries skip their series; *need reports whether either would
-// have used it (the result is then to be discarded and the full evaluation done instead).
-template <class T, bool TRIPLE = true>
+// SERIES = false: no entry evaluates its series; *need reports whether any would have used it (the
+// result is then to be discarded and the full evaluation done instead).  The series are needed
+// only where nodes cluster relative to their distance from w, so most items skip them.
+template <class T, bool SERIES = true>
 C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om, bool *need = nullptr)
 {
     T u[4], w[4];
@@ -509,11 +528,12 @@ C0_HD cplx near_eval_t(const double y[4], const double wd[4], double om, bool *n
     cx<T> V1[3], T1[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        newton_entry<1, T>(y + i, w + i, u + i, L + i, V0[i + 1], T0[i + 1], V0[i], T0[i], V1[i], T1[i]);
+        newton_entry<1, T, SERIES || !CHI0_DEFER_PAIR_SERIES>(y + i, w + i, u + i, L + i, V0[i + 1], T0[i + 1], V0[i],
+                                                               T0[i], V1[i], T1[i], need);
     cx<T> V2[2], T2[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-        newton_entry<2, T, TRIPLE>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i],
+        newton_entry<2, T, SERIES>(y + i, w + i, u + i, L + i, V1[i + 1], T1[i + 1], V1[i], T1[i], V2[i], T2[i],
                                    need);
     // the top entry spans all nodes; in the near branch its span exceeds its distance to w
     const T inv = inv_s;
@@ -533,8 +553,8 @@ C0_HD cplx near_eval(const double y[4], const double w[4], double om) { return n
 // near-degenerate tetrahedra (near_degenerate below).
 C0_HD cplx near_eval32(const double y[4], const double w[4], double om) { return near_eval_t<float>(y, w, om); }
 
-// The near branch without the series of its two 3-node entries, for callers that evaluate the
-// few items whose 3-node entries cluster (need = true) again with near_eval / near_eval32.
+// The near branch without the entry series, for callers that evaluate the items whose entries
+// cluster (need = true) again with near_eval / near_eval32.
 C0_HD cplx near_eval_fast(const double y[4], const double w[4], double om, bool &need)
 {
     need = false;

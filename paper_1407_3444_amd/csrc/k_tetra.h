@@ -292,6 +292,13 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
+__device__ __forceinline__ int wave_sum(int x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
 
 // 1/d in FP32: hardware estimate + one Newton step
 __device__ __forceinline__ float recip32(float d)
@@ -353,14 +360,16 @@ __device__ __forceinline__ void horner_slots_lds(const double *a, const double *
 // in the mixed form, items of the FP32 evaluation at the top (rows kQCap-1, kQCap-2, ...).
 // Lanes with an empty end idle; the loop ends when that end is empty in every lane.
 // Evaluates the lane's queued near items (tetrahedron r, slot s) and empties the queue.  With
-// TWO_PASS (the FP64 form) a first pass skips the series of the 3-node Newton entries, which few
-// items need (their nodes must cluster within theta of their distance from w) but which would
-// otherwise cost every wave that holds one such item; those items are set aside in queue
+// TWO_PASS (the FP64 form) a first pass skips the Taylor series of the Newton entries, which few
+// items need (the entry's nodes must cluster within theta of their distance from w) but which
+// would otherwise cost every wave that holds one such item; those items are set aside in queue
 // positions already consumed and evaluated in full by a second pass.  The FP32 near branch is
-// cheap enough that the second pass does not pay; it takes one pass.
+// cheap enough that the second pass does not pay; it takes one pass.  With a counter (census),
+// the items evaluated by the second pass are counted.
 template <int NSLOT, bool F32, bool TWO_PASS = false, class Rec>
 __device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kWave], int &qn, int lane,
-                                           const double *__restrict__ omega, cplx *acc)
+                                           const double *__restrict__ omega, cplx *acc,
+                                           unsigned long long *redo_count = nullptr)
 {
     const int top = qn;
     int nredo = 0;
@@ -396,6 +405,7 @@ __device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kW
             }
         }
     }
+    if (TWO_PASS && redo_count) *redo_count += (unsigned long long)wave_sum(nredo);
     while (TWO_PASS && __any(nredo > 0)) {
         if (nredo > 0) {
             --nredo;
@@ -412,7 +422,7 @@ __device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kW
 
 // Work counted by the census instantiation (COUNT) of the dynamic body, wave totals.
 struct WorkCount {
-    unsigned long long units, tets, near, far, terms;
+    unsigned long long units, tets, near, far, terms, redo;
 };
 
 // One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
@@ -635,14 +645,15 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                             }
                         }
                     }
-                    if (__any(qn + qn32 > kQCap - NSLOT)) {
-                        drain_near<NSLOT, false, !MIXED>(list, queue, qn, lane, omega, acc);
-                        if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
-                    }
+                }
+                // one drain site (the near evaluations are long; one inlined copy keeps the kernel
+                // within the instruction cache): when a queue may not hold the next tetrahedron's
+                // items, and after the list's last tetrahedron
+                if (r == nrec - 1 || __any(qn + qn32 > kQCap - NSLOT)) {
+                    drain_near<NSLOT, false, !MIXED>(list, queue, qn, lane, omega, acc, COUNT ? &wc->redo : nullptr);
+                    if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
                 }
             }
-            drain_near<NSLOT, false, !MIXED>(list, queue, qn, lane, omega, acc);
-            if (MIXED) drain_near<NSLOT, true>(list, queue, qn32, lane, omega, acc);
             __syncthreads();
         }
     }

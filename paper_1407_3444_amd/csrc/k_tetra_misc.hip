@@ -149,7 +149,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void te
 // kMaxOmegaPerLaunch frequencies), instantiated with counters: units with a non-empty carved
 // region, final tetrahedra, (final tetrahedron, frequency) evaluations of the near branch, far
 // evaluations (one per tetrahedron and frequency on the per-tetrahedron path, one per list and
-// frequency where a whole list is evaluated as one series) and the series terms they use.
+// frequency where a whole list is evaluated as one series), the series terms they use, and the
+// near evaluations repeated in full because an entry's nodes cluster (FP64 form).
 template <bool MIXED, bool LIST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void census_kernel(
     MeshDev M, BatchDev B, int nblocks, const double *__restrict__ omega, int nw, double *__restrict__ partial,
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
     __shared__ DynRec<MIXED> list[kCapDyn];
     __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
-    WorkCount wc = {0, 0, 0, 0, 0};
+    WorkCount wc = {0, 0, 0, 0, 0, 0};
     dynamic_body<8, MIXED, LIST, true>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
                                        partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue, &wc,
                                        count_tets != 0);
@@ -168,6 +169,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
         atomicAdd(&counts[2], wc.near);
         atomicAdd(&counts[3], wc.far);
         atomicAdd(&counts[4], wc.terms);
+        atomicAdd(&counts[5], wc.redo);
     }
 }
 

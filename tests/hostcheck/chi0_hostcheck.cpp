@@ -177,7 +177,7 @@ void hc_near(const double *y, const double *w, double om, int fp32, double *out)
 // Imaginary part alone (delta weights) on sorted nodes.
 double hc_near_im(const double *y, const double *w, double om) { return near_im(y, w, om); }
 
-// The first pass of the kernels' near drain (3-node entry series skipped): returns need and the
+// The first pass of the kernels' near drain (entry series skipped): returns need and the
 // value in out[0..1].
 int hc_near_fast(const double *y, const double *w, double om, int fp32, double *out)
 {
