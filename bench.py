@@ -32,38 +32,109 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 flops per evaluation, counted from the formulas the tetrahedron kernel evaluates
-# (an FMA counts 2, a reciprocal or division 1, a logarithm 20):
-#   far  (final tetrahedron, w; or a whole list of final tetrahedra, w, where the list is one
-#        series): d = w - c (1), |d| rho test (1), reciprocal 1/d from the hardware estimate and
-#        two Newton steps (1 + 8), accumulate (2): 11 + 2 per series term (the census counts the
-#        terms each far evaluation uses; a Horner FMA per term beyond the first, so an n-term
-#        series costs 11 + 2 n)
-#   near (final tetrahedron, w): 4 leaves (log 20 + h, h' with derivative 13 each: 132),
-#        three 2-node entries (recursion 16 + 12-term series: complex low orders 61 + 9 real
-#        terms x 8 = 133, test 2: 3 x 151 + 3 = 456), two 3-node entries (recursion 16 + series:
-#        low orders 47 + 10 real terms x 16 = 207, test 2: 2 x 225 = 450), top entry 12,
-#        accumulate 2
-#   prep (per final tetrahedron): 40 far-series coefficients with W-derivatives (23 each) + 6
-FLOPS_FAR_BASE = 11
+
+def _metrics():
+    """The parity metric shared with the tests (tests/metrics.py)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("tests_metrics", os.path.join(ROOT, "tests", "metrics.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    sys.modules["tests_metrics"] = mod
+    return mod
+
+# Flops of the formulas as the tetrahedron kernel executes them, counted from the source: an FMA
+# counts 2, an add, subtract or multiply 1, the hardware reciprocal estimate 1 (the reciprocal
+# routine is the estimate plus three FMAs: 7), frexp, compares and selects 0.  Work a kernel computes
+# and then discards is not counted.  FP64 form:
+#   far evaluation (final tetrahedron, w; or a list of final tetrahedra summed into one series, w):
+#        w - c 1, reciprocal 7, final accumulate 2 -> 10, plus 2 per series term (one Horner FMA);
+#        the census counts the terms each evaluation uses
+#   near evaluation, first pass (every near item): leaves 4 x (u 1, |u|/span 1, logarithm 41, u^3 L
+#        4, W h' 8) = 220; span reciprocal 8; five Newton entries (span 1, reciprocal 7, value and
+#        W-derivative 14, series test 1) = 115; top entry 14; accumulate 2 -> 359
+#   near evaluation repeated in full (items whose entries cluster, counted by the census):
+#        359 + three 2-node entry series of 8 terms (95 each) + two 3-node entry series of 12 terms
+#        (205 each) -> 1054
+#   per final tetrahedron: centre and half-span 4, 50 series coefficients with W-derivatives
+#        (23 each) and offsets 4, class and flags 12 -> 1170; carving (edge parameters and
+#        interpolated corners of the written pieces) about 40
+#   the logarithm (own routine): range reduction 3, reciprocal 7, 11-term atanh series 23, scale
+#        and ln2 terms 8 -> 41
+FLOPS_FAR_BASE = 10
 FLOPS_PER_TERM = 2
-FLOPS_NEAR = 1052
-FLOPS_PREP = 926
-FP64_PEAK_TFLOPS = 78.6
+FLOPS_NEAR_FIRST = 359
+FLOPS_NEAR_FULL = 1054
+FLOPS_PER_FINAL_TET = 1170 + 40
+# Mixed form: the series in FP32 (20 terms at ratio 0.4), the near branch in FP32 except near-
+# degenerate tetrahedra; the same formulas with the FP32 logarithm (hardware, 3) and 10-term
+# entry series, one pass: 886 per near evaluation; coefficients still FP64 (20 terms: 480).
+FLOPS_NEAR_FULL_FP32 = 886
+FLOPS_PER_FINAL_TET_MIXED = 480 + 16 + 40
+FP64_PEAK_TFLOPS = 78.6      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
+FP32_PEAK_TFLOPS = 157.3     # published FP32 vector peak (packed FP32; this library is built without it)
 METRIC = "chi0 band-pair*tetra*omega updates/s, mixed vs FP64 GPU, at stated rel error"
-VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error per q are under 'mixed'"   # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
+VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error per q are under 'mixed'"
 
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "0eb40fa6ade9307d"
-TRAFFIC_BYTES_PER_LAUNCH = (529870 * 2.0 + 476736 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA = "3e0b84d2b9f7bf05"
+TRAFFIC_BYTES_PER_LAUNCH = (333731.5 * 2.0 + 131072 * 1.0) * 1024
 
 
-def census_flops(census: dict) -> int:
-    """Algorithmic FP64 flops of a dynamic call from its work census."""
+def census_flops(census: dict, mixed: bool = False) -> int:
+    """Flops of a dynamic call from its work census (the counts above)."""
+    if mixed:
+        return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
+                + census["near_evals"] * FLOPS_NEAR_FULL_FP32
+                + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET_MIXED)
     return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
-            + census["near_evals"] * FLOPS_NEAR + census["final_tetrahedra"] * FLOPS_PREP)
+            + census["near_evals"] * FLOPS_NEAR_FIRST + census.get("near_redo", 0) * FLOPS_NEAR_FULL
+            + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET)
+
+
+def host_cores() -> dict:
+    """The host cores this process may use (the CPU baseline runs on all of them), and the CPU."""
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": threads, "nproc": os.cpu_count(), "affinity": avail, "cpu_model": model}
+
+
+def input_manifest(wl) -> str:
+    """SHA-256 over every input array of a workload (energies, eigenvectors, k+q data, omega), in a
+    fixed order: the GPU run and the CPU baseline read these same bytes."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (wl.eps_k, wl.c_k, wl.omega):
+        if a is not None:
+            h.update(np.ascontiguousarray(a).tobytes())
+    for q in wl.qs:
+        for a in (q.eps_kq, q.c_kq):
+            if a is not None:
+                h.update(np.ascontiguousarray(a).tobytes())
+        if q.shift is not None:
+            h.update(np.asarray(q.shift, dtype=np.int64).tobytes())
+    return h.hexdigest()
+
+
+def timed_median(fn, reps: int = 3):
+    """Median wall time of reps calls of fn (and the last result)."""
+    times, out = [], None
+    for _ in range(reps):
+        t = time.time()
+        out = fn()
+        times.append(time.time() - t)
+    return float(np.median(times)), out
 
 
 # The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch).
@@ -142,7 +213,7 @@ def bench_static(args, wl, desc):
               "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}}
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_cores()["threads"]
         t1 = time.time()
         if args.pairs:
             ref = oracle.chi0_pairs(wl, 0, nthreads=threads)[:, :, 0].real
@@ -261,7 +332,7 @@ def bench_pw(args):
 
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_cores()["threads"]
         t1 = time.time()
         ref = oracle.chi0(wl, 0, nthreads=threads)[0].real
         dt = time.time() - t1
@@ -304,7 +375,8 @@ def bench_iw(args):
     qs = [lib.Q(eps_kq=torch.from_numpy(a).to(dev), c_kq=torch.from_numpy(b).to(dev)) for a, b in entries]
     ws = plan.workspace(len(qs), nw)
     out = torch.empty((len(q_list), nw, 2), dtype=torch.float64, device=dev)
-    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0}
+    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0,
+              "near_redo": 0}
     for i in range(0, len(qs), 16):
         cz = plan.census(qs[i:i + 16], om, workspace=ws)
         for k in census:
@@ -372,7 +444,7 @@ def bench_iw(args):
                                    "max_rel_difference_vs_wedge": diff, "census": mcensus}}
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_cores()["threads"]
         sample_g, sample_w = list(range(0, 48, 4)), [0, 36, 73, 109, 146, 182, 219, 255]
         t1 = time.time()
         ref = oracle.chi0_iw(e, c, [entries[g] for g in sample_g], tets, vol, omega[sample_w], mu=mu,
@@ -428,7 +500,8 @@ def bench_batch(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     seq_out = [torch.empty((len(i.qs), int(i.omega.shape[0]), 2), dtype=torch.float64, device=dev)
                for i in insts]
-    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0}
+    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0,
+              "near_redo": 0}
     for p, i in zip(plans, insts):
         c = p.census(i.qs, i.omega, workspace=ws)
         for k in census:
@@ -459,7 +532,8 @@ def bench_batch(args):
     mbatch = lib.Chi0Batch(m_insts, workgroups=args.batch_workgroups, use_graph=True)
     m_ms = timed(mbatch.run, args.steps)
     m_np = [torch.view_as_complex(i.chi).cpu().numpy() for i in m_insts]
-    per_q = np.concatenate([np.max(np.abs(a - b), axis=1) / np.max(np.abs(b), axis=1) for a, b in zip(m_np, seq_np)])
+    _per_result = _metrics().per_result
+    per_q = np.concatenate([_per_result(a, b).max(axis=1) for a, b in zip(m_np, seq_np)])
     log(f"batched mixed (graph): {m_ms:.1f} ms/step, max rel err {per_q.max():.2e}")
     mbatch.close()
 
@@ -484,12 +558,13 @@ def bench_batch(args):
         "mixed": {"bf16x3_batched": {"value": units / (m_ms * 1e-3), "ms_per_step": m_ms,
                                      "speedup_vs_sequential_fp64": seq_ms / m_ms,
                                      "speedup_vs_batched_fp64": b_ms / m_ms,
-                                     "max_rel_err_per_q_max": float(per_q.max()),
-                                     "max_rel_err_per_q_mean": float(per_q.mean())}},
+                                     "rel_err_vs_fp64_gpu_per_q_max": float(per_q.max()),
+                                     "rel_err_vs_fp64_gpu_per_q_mean": float(per_q.mean()),
+                                     "metric": "per result: |d| / max(|ref|, 1e-3 max_w |ref|)"}},
     }
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        threads = host_cores()["threads"]
         wl = wls[15][0]
         sample_w = list(range(0, len(wl.omega), max(1, len(wl.omega) // 4)))
         t1 = time.time()
@@ -516,7 +591,7 @@ def main():
     ap.add_argument("--workload", default="tetra_dynamic",
                     choices=["tetra_dynamic", "bcc_dynamic", "tetra_static", "sc_cma", "batch", "pw_static",
                              "iw_cubic"])
-    ap.add_argument("--batch-nq-div", type=int, default=8,
+    ap.add_argument("--batch-nq-div", type=int, default=1,
                     help="batch workload: divide every instance's q count by this (1 = full size)")
     ap.add_argument("--batch-workgroups", type=int, default=0, help="batch workload: K_B workgroups (0 = default)")
     ap.add_argument("--tune", action="store_true", help="batch workload: autotune the workgroups first")
@@ -626,7 +701,9 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "tetra_dynamic_kernel", "avg_launch_ms": round(avg_ms, 3),
-                "launches_per_step": launches_per_step}
+                "launches_per_step": launches_per_step,
+                "flops_per_launch": flops_per_launch,
+                "count": "census x flops of the formulas as executed (bench.py constants)"}
 
     result = {
         "metric": METRIC, "value_form": VALUE_FORM,
@@ -651,30 +728,84 @@ def main():
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
     }
 
+    # the oracle sample: q index 0 at 8 frequencies on the full mesh; it checks the FP64 and mixed
+    # results and times the CPU baseline
+    sample_w = [0, 73, 146, 219, 292, 365, 438, 511] if nw == 512 else list(range(0, nw, max(1, nw // 8)))[:8]
+    ref_sample = None
+    if not args.no_cpu_baseline:
+        import oracle
+        _m = _metrics()
+        _max_err, _mean_err = _m.max_err, _m.mean_err
+        cores = host_cores()
+        dt, ref_sample = timed_median(lambda: oracle.chi0(wl, 0, omega=wl.omega[sample_w],
+                                                          nthreads=cores["threads"]), reps=3)
+        units = 6 * wl.n_k * nbw * nbw * len(sample_w)
+        got = torch.view_as_complex(out[0]).cpu().numpy()[sample_w]
+        result["cpu_baseline"] = {"value": units / dt, "unit": "updates/s", "cores": cores["threads"],
+                                  "kind": "oracle",
+                                  "sample": f"q index 0, {len(sample_w)} of {nw} w, full "
+                                            f"{'x'.join(map(str, wl.nk))} mesh, median of 3 runs "
+                                            f"({dt:.1f} s each)",
+                                  "cpu_model": cores["cpu_model"], "nproc": cores["nproc"],
+                                  "affinity_cores": cores["affinity"],
+                                  "inputs_sha256": input_manifest(wl)}
+        result["parity_sample"] = {"max_rel_err_vs_oracle": _max_err(got, ref_sample),
+                                   "mean_rel_err_vs_oracle": _mean_err(got, ref_sample),
+                                   "q": 0, "omega_index": sample_w,
+                                   "metric": "per result: |d| / max(|ref|, 1e-3 max_w |ref|)"}
+        log(f"oracle sample {dt:.1f}s (median of 3, {cores['threads']} threads), "
+            f"max rel err {result['parity_sample']['max_rel_err_vs_oracle']:.2e}")
+
     if not args.no_mixed:
-        # mixed form: split BF16 MFMA matrix elements, FP32 far-branch weights, FP64 fallback
-        # and FP64 accumulation; error against this run's FP64 result, per q (normwise over w)
+        # mixed forms: split BF16 / FP16 MFMA matrix elements, FP32 weights with the FP64 near branch
+        # for near-degenerate tetrahedra, FP64 accumulation.  Errors per result (|d| / max(|ref|,
+        # 1e-3 max_w |ref|)): against the FP64 oracle on its sample, and against this run's FP64 GPU
+        # result over every q and frequency.
+        _per_result = _metrics().per_result
         ref64 = torch.view_as_complex(out).cpu().numpy()
         res = {}
         for prec, name in ((1, "bf16x3"), (2, "fp16x3")):
             mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo,
                                  band_hi=hi, precision=prec)
             mout = torch.empty_like(out)
+            mcensus = mplan.census(qs, om, workspace=ws) if name == "bf16x3" else None
             mplan.dynamic(qs, om, workspace=ws, out=mout)
             torch.cuda.synchronize()
+            mplan.profile(True)
+            mplan.read_profile()
             m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             m0.record(stream)
             for i in range(args.steps):
                 mplan.dynamic(qs, om, workspace=ws, out=mout)
             m1.record(stream)
             torch.cuda.synchronize()
+            mprof = mplan.read_profile()
+            mplan.profile(False)
             mms = m0.elapsed_time(m1) / args.steps
             got = torch.view_as_complex(mout).cpu().numpy()
-            per_q = np.max(np.abs(got - ref64), axis=1) / np.max(np.abs(ref64), axis=1)
-            res[name] = {"value": units_per_step / (mms * 1e-3), "ms_per_step": mms,
-                         "speedup_vs_fp64": ms_step / mms, "max_rel_err_per_q_max": float(per_q.max()),
-                         "max_rel_err_per_q_mean": float(per_q.mean())}
-            log(f"mixed {name}: {mms:.1f} ms/step, max rel err {per_q.max():.2e}")
+            err_gpu = _per_result(got, ref64)
+            entry = {"value": units_per_step / (mms * 1e-3), "ms_per_step": mms,
+                     "speedup_vs_fp64": ms_step / mms,
+                     "rel_err_vs_fp64_gpu_per_q_max": float(err_gpu.max(axis=1).max()),
+                     "rel_err_vs_fp64_gpu_per_q_mean": float(err_gpu.mean(axis=1).mean()),
+                     "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in mprof.items()}}
+            if ref_sample is not None:
+                e = _per_result(got[0][sample_w], ref_sample)
+                entry["rel_err_vs_oracle_sample_max"] = float(e.max())
+                entry["rel_err_vs_oracle_sample_mean"] = float(e.mean())
+            if mcensus is not None:
+                mt = mprof["tetra"]
+                m_avg = mt["ms"] / mt["launches"]
+                m_ach = census_flops(mcensus, mixed=True) / (mt["launches"] / args.steps) / (m_avg * 1e-3) / 1e12
+                entry["roofline"] = {"bound": "alu", "achieved": round(m_ach, 3), "peak": FP32_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": round(m_ach / FP32_PEAK_TFLOPS, 4),
+                                     "traffic": None, "kernel": "tetra_dynamic_kernel (mixed form)",
+                                     "avg_launch_ms": round(m_avg, 3),
+                                     "count": "FP32 + FP64 flops from the census (bench.py constants)"}
+                entry["census"] = mcensus
+            res[name] = entry
+            log(f"mixed {name}: {mms:.1f} ms/step, per-result err vs FP64 GPU max {err_gpu.max():.2e}"
+                + (f", vs oracle sample {entry['rel_err_vs_oracle_sample_max']:.2e}" if ref_sample is not None else ""))
             del mplan
         result["mixed"] = res
 
@@ -708,21 +839,7 @@ def main():
                               "im_rel_err_vs_analytic_max": float(err_im.max())}
         log(f"KK route: {kms:.1f} ms/step, Re rel err {err_re.max():.2e}, Im rel err {err_im.max():.2e}")
 
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        sample_w = [0, 73, 146, 219, 292, 365, 438, 511]
-        t1 = time.time()
-        ref = oracle.chi0(wl, 0, omega=wl.omega[sample_w], nthreads=threads)
-        dt = time.time() - t1
-        units = 6 * wl.n_k * nbw * nbw * len(sample_w)
-        got = torch.view_as_complex(out[0]).cpu().numpy()[sample_w]
-        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        result["cpu_baseline"] = {"value": units / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-                                  "sample": f"q index 0, {len(sample_w)} of {nw} w, full "
-                                            f"{'x'.join(map(str, wl.nk))} mesh, {dt:.1f} s"}
-        result["parity_sample"] = {"max_rel_err_vs_oracle": err, "q": 0, "omega_index": sample_w}
-        log(f"oracle sample {dt:.1f}s, rel err {err:.2e}")
+    plan.sync()
     print(json.dumps(result), flush=True)
 
 
