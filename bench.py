@@ -211,6 +211,24 @@ def bench_static(args, wl, desc):
                          "band_pairs": nbw * nbw, "units_per_step": units, "parallelism": "single GPU"},
               "roofline": None,
               "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}}
+    if args.pairs:
+        # band-pair analysis (Sec. III, Fig. 8): the share of each (n at k, m at k+q) pair in chi0 at the
+        # q of largest |chi0|, and the band-truncation convergence: chi0 of the window of n_keep bands
+        # nearest the Fermi level (mean energy closest to mu) is the sum of its (n, m) block
+        pr = out.cpu().numpy()
+        tot = pr.sum(axis=(1, 2))
+        qmax = int(np.argmax(np.abs(tot)))
+        conv = {}
+        for n_keep in range(1, nbw + 1):
+            wlo, whi = synth_band_window(wl.eps_k[lo:hi], n_keep, wl.mu)
+            sub = pr[:, wlo:whi, wlo:whi].sum(axis=(1, 2))
+            rel = np.abs(sub - tot) / np.abs(tot)
+            conv[str(n_keep)] = {"window": [lo + wlo, lo + whi], "rel_diff_vs_all_max": float(rel.max()),
+                                 "rel_diff_vs_all_mean": float(rel.mean())}
+        result["band_pairs"] = {"q_index_of_max": qmax, "chi0_at_q": float(tot[qmax]),
+                                "pair_share_at_q": np.round(pr[qmax] / tot[qmax], 4).tolist(),
+                                "truncation": conv}
+        log("band truncation", {k: round(v["rel_diff_vs_all_max"], 4) for k, v in conv.items()})
     if not args.no_cpu_baseline:
         import oracle
         threads = host_cores()["threads"]
@@ -226,6 +244,11 @@ def bench_static(args, wl, desc):
                                   "kind": "oracle", "sample": f"q index 0 of {len(qs)}, full mesh, {dt:.1f} s"}
         result["parity_sample"] = {"rel_err_vs_oracle": err, "q": 0}
     print(json.dumps(result), flush=True)
+
+
+def synth_band_window(eps, n_keep, mu):
+    import synth
+    return synth.band_window(eps, n_keep, mu)
 
 
 def bench_pw(args):
@@ -600,6 +623,9 @@ def main():
     ap.add_argument("--pairs", action="store_true",
                     help="static workloads: time the band-pair resolved call (chi0_static_pairs)")
     ap.add_argument("--n-keep", type=int, default=9, help="band window of bcc_dynamic")
+    ap.add_argument("--sweep", action="store_true",
+                    help="bcc_dynamic with all 9 bands: also time the 7- and 5-band windows and report "
+                         "their difference from the all-band result per q")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM byte counters)")
@@ -838,6 +864,37 @@ def main():
                               "re_rel_err_vs_analytic_per_q_mean": float(err_re.mean()),
                               "im_rel_err_vs_analytic_max": float(err_im.max())}
         log(f"KK route: {kms:.1f} ms/step, Re rel err {err_re.max():.2e}, Im rel err {err_im.max():.2e}")
+
+    if args.sweep and args.workload == "bcc_dynamic" and (lo, hi) == (0, wl.n_bands):
+        # band truncation (Sec. III): the 7- and 5-band windows nearest the Fermi level (mean energy
+        # closest to mu) against the sum over all 9 bands, per q: max_w |chi_n - chi_9| / max_w |chi_9|
+        import synth
+        ref_all = torch.view_as_complex(out).cpu().numpy()
+        sweep = {}
+        for n_keep in (7, 5):
+            wlo, whi = synth.band_window(wl.eps_k, n_keep, wl.mu)
+            splan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=wlo, band_hi=whi)
+            sout = torch.empty_like(out)
+            splan.dynamic(qs, om, workspace=ws, out=sout)
+            torch.cuda.synchronize()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            for i in range(args.steps):
+                splan.dynamic(qs, om, workspace=ws, out=sout)
+            s1.record(stream)
+            torch.cuda.synchronize()
+            sms = s0.elapsed_time(s1) / args.steps
+            got = torch.view_as_complex(sout).cpu().numpy()
+            rel = np.max(np.abs(got - ref_all), axis=1) / np.max(np.abs(ref_all), axis=1)
+            su = len(qs) * 6 * wl.n_k * (whi - wlo) ** 2 * nw
+            sweep[str(n_keep)] = {"window": [wlo, whi], "ms_per_step": sms, "value": su / (sms * 1e-3),
+                                  "rel_diff_vs_all_bands_per_q_max": float(rel.max()),
+                                  "rel_diff_vs_all_bands_per_q_mean": float(rel.mean()),
+                                  "rel_diff_vs_all_bands_per_q": [round(float(v), 4) for v in rel]}
+            log(f"band window {n_keep} {wlo}..{whi}: {sms:.1f} ms/step, max rel diff vs all bands {rel.max():.3f}")
+            splan.sync()
+            del splan
+        result["band_truncation"] = sweep
 
     plan.sync()
     print(json.dumps(result), flush=True)

@@ -531,3 +531,24 @@ def test_full_size_dynamic_q_in_the_last_launch():
         err = _relerr(got[i][sample], ref)
         _say(f"q index {44 + i}: max per-result error {err:.2e}")
         assert err <= TOL, (i, got[i][sample], ref)
+
+
+def test_band_truncation_sub_windows_from_pair_resolved_output():
+    """Band truncation (Sec. III: sums over the bands near the Fermi level): the pair-resolved static
+    chi0 of the full 9-band window of the bcc model, summed over the (n, m) block of a narrower
+    window, is chi0 of that window; checked against the oracle for the 5- and 7-band windows of the
+    window rule (mean energy closest to mu) and two off-centre windows."""
+    torch = _torch()
+    wl = synth.make_workload("bcc_dynamic", nk=(8, 8, 8), nq=8, q_subset=[1, 5], nw=8, n_keep=9)
+    wl.static = True
+    plan, qs = _plan(wl)
+    _say("band-truncation windows from pairs, bcc 8^3")
+    pairs = plan.static_pairs(qs).cpu().numpy()
+    windows = [synth.band_window(wl.eps_k, 5, wl.mu), synth.band_window(wl.eps_k, 7, wl.mu), (0, 4), (6, 9)]
+    for i in range(len(wl.qs)):
+        for lo, hi in windows:
+            got = pairs[i, lo:hi, lo:hi].sum()
+            wl.band_lo, wl.band_hi = lo, hi
+            ref = oracle.chi0(wl, i, omega=[0.0])[0].real
+            wl.band_lo, wl.band_hi = 0, 9
+            assert abs(got - ref) <= TOL * max(abs(ref), 1e-3 * abs(pairs[i].sum())), (i, lo, hi, got, ref)
