@@ -72,6 +72,7 @@ FLOPS_NEAR_FULL_FP32 = 886
 FLOPS_PER_FINAL_TET_MIXED = 480 + 16 + 40
 FP64_PEAK_TFLOPS = 78.6      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 FP32_PEAK_TFLOPS = 157.3     # published FP32 vector peak (packed FP32; this library is built without it)
+HBM_PEAK_GBS = 8000.0        # published HBM3E bandwidth
 METRIC = "chi0 band-pair*tetra*omega updates/s, mixed vs FP64 GPU, at stated rel error"
 VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error per q are under 'mixed'"
 
@@ -352,6 +353,52 @@ def bench_pw(args):
                                     "max_rel_diff_of_W": diff}
     log(f"vendor batched zgemm: {gms:.3f} ms/q; ours {avg_ms / q_per_launch:.3f} ms/q; W rel diff {diff:.2e}")
     del a_h, b, m, w_lib
+
+    # split-precision forms of the same step: time, matrix-element and chi0 errors against this run's
+    # FP64 result, and the roofline of their contraction kernel (HBM: the FP64 coefficients are read
+    # as they are; the matrix cores do 24 flops per band pair and basis function, two real GEMMs of
+    # doubled depth with three products each)
+    ref64 = out.clone()
+    mixed = {}
+    for prec, name in ((1, "bf16x3"), (2, "fp16x3")):
+        mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
+                             precision=prec)
+        mout = torch.empty_like(out)
+        for _ in range(max(1, args.warmup)):
+            mplan.static(qs, workspace=ws, out=mout)
+        torch.cuda.synchronize()
+        mplan.profile(True)
+        mplan.read_profile()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record(stream)
+        for _ in range(args.steps):
+            mplan.static(qs, workspace=ws, out=mout)
+        m1.record(stream)
+        torch.cuda.synchronize()
+        mms = m0.elapsed_time(m1) / args.steps
+        mprof = mplan.read_profile()
+        mplan.profile(False)
+        mcon = mprof["contract"]
+        m_avg = mcon["ms"] / mcon["launches"]
+        w_split = mplan.matrix_elements(qs[0])
+        torch.cuda.synchronize()
+        w_err = float((w_split - w_ours).abs().max() / w_ours.abs().max())
+        chi_err = float(((mout - ref64).abs() / ref64.abs()).max())
+        hbm = bytes_launch / (m_avg * 1e-3) / 1e9
+        split_flops = 24.0 * n_pw * nbw * nbw * wl.n_k * q_per_launch
+        mixed[name] = {"ms_per_step": round(mms, 3), "speedup_vs_fp64": round(ms / mms, 3),
+                       "contract_ms_per_launch": round(m_avg, 3),
+                       "contract_speedup_vs_fp64": round(avg_ms / m_avg, 3),
+                       "max_rel_err_of_W_vs_fp64": w_err, "max_rel_err_of_chi0_vs_fp64": chi_err,
+                       "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                                    "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+                                    "kernel": "contract_pw_split_kernel",
+                                    "algorithmic_bytes_per_launch": bytes_launch,
+                                    "mfma_tflops": round(split_flops / (m_avg * 1e-3) / 1e12, 1)}}
+        log(f"{name}: {mms:.2f} ms/step, contraction {m_avg:.3f} ms/launch ({hbm:.0f} GB/s), "
+            f"W err {w_err:.2e}, chi0 err {chi_err:.2e}")
+        del mplan, mout, w_split
+    result["mixed"] = mixed
 
     if not args.no_cpu_baseline:
         import oracle

@@ -81,8 +81,8 @@ typedef struct chi0_desc {
     int32_t n_bands;        /* bands stored in the energy/eigenvector arrays (1..64) */
     int32_t n_orb;          /* basis functions per eigenvector: orbitals (1..64), or up to 16384
                                plane waves (a basis above 64 takes the plane-wave MFMA contraction,
-                               one wave per q sharing the k operand, always in FP64); ignored
-                               under cma */
+                               one wave per q sharing the k operand, in the precision below);
+                               ignored under cma */
     int32_t band_lo;        /* first band of the summation window (Sec. III band truncation) */
     int32_t band_hi;        /* one past the last band; <= 0 means n_bands; window <= 32 bands */
     int32_t cma;            /* 1: constant matrix elements W = 1 (Sec. III), eigenvectors unused */
@@ -91,7 +91,7 @@ typedef struct chi0_desc {
                                   1/(w-D+i0) - 1/(w+D+i0)  (equal to form 0 under time reversal) */
     int32_t precision;      /* 0: FP64 everywhere.
                                1: mixed: matrix elements from BF16 MFMA with hi+lo split operands
-                                  and FP32 accumulation; dynamic weights of final tetrahedra in
+                                  and FP32 accumulation (orbital and plane-wave bases alike); dynamic weights of final tetrahedra in
                                   FP32 (far series and near branch), except that near-degenerate
                                   final tetrahedra (degen_tol_ev, degen_rel_tol below) keep the
                                   FP64 near branch; carving, differences of energies and the chi0

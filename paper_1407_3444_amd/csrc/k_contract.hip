@@ -21,6 +21,20 @@ constexpr int kKPerBlock = 16;
 
 typedef double Tile[16][kKPerBlock + 1];
 
+// Mesh index of k + q: the shifted mesh point, or k itself when the k+q data are given explicitly.
+__device__ __forceinline__ int64_t shifted_k(const MeshDev &M, const QDev &Q, int64_t k)
+{
+    if (Q.explicit_kq) return k;
+    int i2 = (int)(k % M.n3);
+    const int64_t t = k / M.n3;
+    int i1 = (int)(t % M.n2);
+    int i0 = (int)(t / M.n2);
+    i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
+    i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
+    i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
+    return ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
+}
+
 // One workgroup of FP64 matrix elements: k = k0 .. k0+15 of one q.
 __device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &Q, int64_t k0, Tile *tile)
 {
@@ -38,17 +52,7 @@ __device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &
             for (int kl = 0; kl < kKPerBlock; ++kl) {
                 const int64_t k = k0 + kl;
                 if (k >= nk) break;
-                int64_t kq = k;
-                if (!Q.explicit_kq) {
-                    int i2 = (int)(k % M.n3);
-                    const int64_t t = k / M.n3;
-                    int i1 = (int)(t % M.n2);
-                    int i0 = (int)(t / M.n2);
-                    i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
-                    i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
-                    i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
-                    kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
-                }
+                const int64_t kq = shifted_k(M, Q, k);
                 dbl4 accr = {0.0, 0.0, 0.0, 0.0};
                 dbl4 acci = {0.0, 0.0, 0.0, 0.0};
                 for (int o0 = 0; o0 < no; o0 += 4) {
@@ -91,58 +95,105 @@ __device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &
 }
 
 // ---------------------------------------------------------------------------
-// Split-precision form: 16-bit MFMA with FP32 accumulation and hi + lo operands.
-// Every FP64 operand x is split as x = hi + lo with hi = round16(x) and
-// lo = round16((x - hi) * S) / S (S = 2^11 for FP16, whose exponent range would flush
-// small remainders; S = 1 for BF16), and a product is taken as
-// hi*hi + (hi*lo + lo*hi) / S: three MFMAs.  hi and lo together carry 2 x 8 significant bits
-// for BF16 and 2 x 11 for FP16, so the dropped lo*lo term and the rounding of lo leave a relative
-// error of about 2^-16 per product for BF16 (well above the FP32 accumulation's 2^-24) and about
-// 2^-22 for FP16.  The complex product is folded into real GEMMs over a doubled
-// reduction axis:  Re M = [Cr Ci] . [Br; Bi],  Im M = [Cr Ci] . [Bi; -Br].
+// Split-precision forms: 16-bit MFMA with FP32 accumulation and hi + lo operands, on the gfx950
+// 16x16x32 instructions (v_mfma_f32_16x16x32_{bf16,f16}).  Every FP64 operand x is taken to FP32
+// and split as x = hi + lo with hi = round16(x) and lo = round16((x - hi) * S) / S (S = 2^11 for
+// FP16, whose exponent range would flush small remainders; S = 1 for BF16); a product is taken as
+// hi*hi + (hi*lo + lo*hi) / S: three MFMAs.  hi and lo together carry 2 x 8 significant bits for
+// BF16 and 2 x 11 for FP16, so the dropped lo*lo term and the rounding of lo leave a relative error
+// of about 2^-16 per product for BF16 (well above the FP32 accumulation's 2^-24) and about 2^-22
+// for FP16.
+//
+// The complex product is folded into two real GEMMs over a doubled reduction axis.  One MFMA
+// covers 16 orbitals: lane (row, g) holds the real parts of orbitals 4g .. 4g+3 of the step and
+// then their imaginary parts, so with a = C(k), b = C(k+q)
+//     A = [ar; ai],  B_re = [br; bi],  B_im = [bi; -br],   Re M = A . B_re,  Im M = A . B_im.
+// B_im is B_re with its two halves exchanged and the second negated: a register permutation and a
+// sign flip of packed 16-bit values, so every coefficient is split once.  Which reduction slot the
+// hardware gives each of a lane's eight values does not matter: A and B use the same assignment.
+// Per 16 orbitals and 16x16 tile pair: six MFMAs (hi.hi, hi.lo, lo.hi for Re and for Im).
 // ---------------------------------------------------------------------------
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
-typedef _Float16 half4 __attribute__((ext_vector_type(4)));
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ short to_bf16(float f)
-{
-    // round to nearest even (finite inputs)
-    const unsigned u = __float_as_uint(f);
-    return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
+constexpr unsigned kSign2 = 0x80008000u;   // sign bits of two packed 16-bit values
 
-__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
-
+// Two FP64 values -> packed 16-bit high parts and low parts (round to nearest even; the low parts
+// scaled by 2^11 for FP16).
 template <bool FP16>
-struct Split4 {
-    half4 hh, hl;
-    bf16x4 bh, bl;
-};
-
-template <bool FP16>
-__device__ __forceinline__ void split_value(double x, int j, Split4<FP16> &s)
+__device__ __forceinline__ void split2(double x, double y, unsigned &hi, unsigned &lo)
 {
+    const flt2 f = {(float)x, (float)y};
     if (FP16) {
-        const _Float16 hi = (_Float16)x;
-        const _Float16 lo = (_Float16)((x - (double)hi) * 2048.0);
-        s.hh[j] = hi;
-        s.hl[j] = lo;
+        const f16x2 h = __builtin_convertvector(f, f16x2);
+        const flt2 r = (f - __builtin_convertvector(h, flt2)) * 2048.0f;
+        hi = __builtin_bit_cast(unsigned, h);
+        lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, f16x2));
     } else {
-        const short hi = to_bf16((float)x);
-        const short lo = to_bf16((float)(x - (double)from_bf16(hi)));
-        s.bh[j] = hi;
-        s.bl[j] = lo;
+        const bf16x2 h = __builtin_convertvector(f, bf16x2);
+        const flt2 r = f - __builtin_convertvector(h, flt2);
+        hi = __builtin_bit_cast(unsigned, h);
+        lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
     }
 }
 
 template <bool FP16>
-__device__ __forceinline__ flt4 mfma16(const Split4<FP16> &a, bool a_lo, const Split4<FP16> &b, bool b_lo, flt4 c)
+__device__ __forceinline__ flt4 mfma32(u32x4 a, u32x4 b, flt4 c)
 {
     if (FP16)
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(a_lo ? a.hl : a.hh, b_lo ? b.hl : b.hh, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_lo ? a.bl : a.bh, b_lo ? b.bl : b.bh, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// The split operand of 4 orbitals of one lane: hi and lo of [re0..re3, im0..im3].
+template <bool FP16>
+__device__ __forceinline__ void split_op(const double2 (&v)[4], u32x4 &hi, u32x4 &lo)
+{
+    unsigned h[4], l[4];
+    split2<FP16>(v[0].x, v[1].x, h[0], l[0]);
+    split2<FP16>(v[2].x, v[3].x, h[1], l[1]);
+    split2<FP16>(v[0].y, v[1].y, h[2], l[2]);
+    split2<FP16>(v[2].y, v[3].y, h[3], l[3]);
+    hi = u32x4{h[0], h[1], h[2], h[3]};
+    lo = u32x4{l[0], l[1], l[2], l[3]};
+}
+
+// [br; bi] -> [bi; -br]
+__device__ __forceinline__ u32x4 rot_op(u32x4 b) { return u32x4{b[2], b[3], b[0] ^ kSign2, b[1] ^ kSign2}; }
+
+// Re and Im accumulators of one 16x16 tile pair (main hi.hi products and the scaled corrections).
+struct SplitAcc {
+    flt4 re, re_c, im, im_c;
+};
+
+template <bool FP16>
+__device__ __forceinline__ void split_step(SplitAcc &c, u32x4 ah, u32x4 al, u32x4 bh, u32x4 bl)
+{
+    c.re = mfma32<FP16>(ah, bh, c.re);
+    c.re_c = mfma32<FP16>(ah, bl, c.re_c);
+    c.re_c = mfma32<FP16>(al, bh, c.re_c);
+    const u32x4 ih = rot_op(bh), il = rot_op(bl);
+    c.im = mfma32<FP16>(ah, ih, c.im);
+    c.im_c = mfma32<FP16>(ah, il, c.im_c);
+    c.im_c = mfma32<FP16>(al, ih, c.im_c);
+}
+
+// |M|^2 of accumulator element v
+template <bool FP16>
+__device__ __forceinline__ double split_abs2(const SplitAcc &c, int v)
+{
+    const float inv_s = FP16 ? 1.0f / 2048.0f : 1.0f;
+    const double mr = (double)fmaf(c.re_c[v], inv_s, c.re[v]);
+    const double mi = (double)fmaf(c.im_c[v], inv_s, c.im[v]);
+    return mr * mr + mi * mi;
 }
 
 // One workgroup of split-precision matrix elements: k = k0 .. k0+15 of one q.
@@ -151,12 +202,10 @@ __device__ __forceinline__ void contract_split_body(const MeshDev &M, const QDev
 {
     const int lane = threadIdx.x;
     const int row = lane & 15;      // A row (band n) / B column (band m)
-    const int kq4 = lane >> 4;      // which 4 of the 16 reduction indices of a step
+    const int g = lane >> 4;        // orbitals 4g .. 4g+3 of a step of 16
     const int64_t nk = M.nk;
     const int ntile = (M.nbw + 15) / 16;
     const int nb = M.nb, no = M.no;
-    const int kred = 2 * no;        // reduction axis: orbitals (real parts), then orbitals (imaginary)
-    const float inv_s = FP16 ? 1.0f / 2048.0f : 1.0f;
 
     for (int tn = 0; tn < ntile; ++tn) {
         for (int tm = 0; tm < ntile; ++tm) {
@@ -165,54 +214,26 @@ __device__ __forceinline__ void contract_split_body(const MeshDev &M, const QDev
             for (int kl = 0; kl < kKPerBlock; ++kl) {
                 const int64_t k = k0 + kl;
                 if (k >= nk) break;
-                int64_t kq = k;
-                if (!Q.explicit_kq) {
-                    int i2 = (int)(k % M.n3);
-                    const int64_t t = k / M.n3;
-                    int i1 = (int)(t % M.n2);
-                    int i0 = (int)(t / M.n2);
-                    i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
-                    i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
-                    i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
-                    kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
-                }
-                flt4 re_main = {0.f, 0.f, 0.f, 0.f}, re_corr = {0.f, 0.f, 0.f, 0.f};
-                flt4 im_main = {0.f, 0.f, 0.f, 0.f}, im_corr = {0.f, 0.f, 0.f, 0.f};
-                for (int r0 = 0; r0 < kred; r0 += 16) {
-                    Split4<FP16> a, bre, bim;
+                const int64_t kq = shifted_k(M, Q, k);
+                SplitAcc acc;
+                acc.re = acc.re_c = acc.im = acc.im_c = flt4{0.f, 0.f, 0.f, 0.f};
+                for (int o0 = 0; o0 < no; o0 += 16) {
+                    double2 av[4], bv[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int r = r0 + 4 * kq4 + j;
-                        const bool imag = r >= no;
-                        const int o = imag ? r - no : r;
-                        double av = 0.0, brv = 0.0, biv = 0.0;
-                        if (r < kred && n < M.nbw) {
-                            const double *p = M.c_k + 2 * ((k * no + o) * nb + M.lo + n);
-                            av = imag ? p[1] : p[0];                // [Cr Ci]
-                        }
-                        if (r < kred && m < M.nbw) {
-                            const double *p = Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m);
-                            brv = imag ? p[1] : p[0];               // [Br; Bi]
-                            biv = imag ? -p[0] : p[1];              // [Bi; -Br]
-                        }
-                        split_value<FP16>(av, j, a);
-                        split_value<FP16>(brv, j, bre);
-                        split_value<FP16>(biv, j, bim);
+                    for (int i = 0; i < 4; ++i) {
+                        const int o = o0 + 4 * g + i;
+                        av[i] = bv[i] = double2{0.0, 0.0};
+                        if (o < no && n < M.nbw) av[i] = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((k * no + o) * nb + M.lo + n));
+                        if (o < no && m < M.nbw) bv[i] = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m));
                     }
-                    re_main = mfma16<FP16>(a, false, bre, false, re_main);
-                    re_corr = mfma16<FP16>(a, false, bre, true, re_corr);
-                    re_corr = mfma16<FP16>(a, true, bre, false, re_corr);
-                    im_main = mfma16<FP16>(a, false, bim, false, im_main);
-                    im_corr = mfma16<FP16>(a, false, bim, true, im_corr);
-                    im_corr = mfma16<FP16>(a, true, bim, false, im_corr);
+                    u32x4 ah, al, bh, bl;
+                    split_op<FP16>(av, ah, al);
+                    split_op<FP16>(bv, bh, bl);
+                    split_step<FP16>(acc, ah, al, bh, bl);
                 }
-                // accumulator element v of this lane is D[4 kq4 + v][row] for the 16x16x16 MFMA
+                // accumulator element v of this lane is D[4 g + v][row] for the 16x16 MFMAs
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float mr = fmaf(re_corr[v], inv_s, re_main[v]);
-                    const float mi = fmaf(im_corr[v], inv_s, im_main[v]);
-                    tile[4 * kq4 + v][row][kl] = (double)(mr * mr + mi * mi);
-                }
+                for (int v = 0; v < 4; ++v) tile[4 * g + v][row][kl] = split_abs2<FP16>(acc, v);
             }
             __syncthreads();
             for (int e = lane; e < 16 * 16 * kKPerBlock; e += 64) {
@@ -263,29 +284,27 @@ constexpr int kPwQ = 8;      // q (waves) per workgroup
 constexpr int kXcd = 8;
 constexpr int kPwDepth = 4;  // steps of operands in flight per wave
 
-// blockDim.x / 64 q per workgroup (kPwQ, or nq when the launch has fewer).
-template <int NT>
-__global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups)
+// The (k, q) of this wave; false past the mesh or the last q.  blockDim.x / 64 q per workgroup
+// (kPwQ, or nq when the launch has fewer).
+__device__ __forceinline__ bool pw_item(const MeshDev &M, int nq, int n_qgroups, int64_t &k, int &qi)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t b = blockIdx.x;
     const int xcd = (int)(b % kXcd);
     const int64_t slot = b / kXcd;
-    const int64_t k = (slot / n_qgroups) * kXcd + xcd;
-    const int qi = (int)(slot % n_qgroups) * (int)(blockDim.x >> 6) + wave;
-    if (k >= M.nk || qi >= nq) return;      // no barriers below: a wave may leave on its own
+    k = (slot / n_qgroups) * kXcd + xcd;
+    qi = (int)(slot % n_qgroups) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    return k < M.nk && qi < nq;
+}
+
+template <int NT>
+__global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t k;
+    int qi;
+    if (!pw_item(M, nq, n_qgroups, k, qi)) return;      // no barriers below: a wave may leave on its own
     const QDev Q = B.q[qi];
-    int64_t kq = k;
-    if (!Q.explicit_kq) {
-        int i2 = (int)(k % M.n3);
-        const int64_t t = k / M.n3;
-        int i1 = (int)(t % M.n2);
-        int i0 = (int)(t / M.n2);
-        i0 += Q.shift[0]; i0 -= i0 >= M.n1 ? M.n1 : 0;
-        i1 += Q.shift[1]; i1 -= i1 >= M.n2 ? M.n2 : 0;
-        i2 += Q.shift[2]; i2 -= i2 >= M.n3 ? M.n3 : 0;
-        kq = ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
-    }
+    const int64_t kq = shifted_k(M, Q, k);
     const int row = lane & 15, kk = lane >> 4;
     const int nb = M.nb, no = M.no;
     // operand rows of this lane: band t*16 + row of C(k) (A) and of C(k+q) (B), orbital o0 + kk
@@ -372,6 +391,87 @@ __global__ __launch_bounds__(64 * kPwQ) void contract_pw_kernel(MeshDev M, Batch
             }
 }
 
+// Split-precision forms for large bases: the workgroup and XCD layout of contract_pw_kernel, the
+// folded two-GEMM product and hi/lo split of the small-basis form (16 orbitals per MFMA step).
+// Coefficients arrive as FP64 and are split as they are used; each lane keeps pw_split_depth(NT)
+// steps of its operands in flight (two for one tile, one for 2 x 2 tiles, whose operands and
+// accumulators would otherwise not fit in 256 registers).
+constexpr int pw_split_depth(int nt) { return nt == 1 ? 2 : 1; }
+
+template <int NT, bool FP16>
+__global__ __launch_bounds__(64 * kPwQ) void contract_pw_split_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t k;
+    int qi;
+    if (!pw_item(M, nq, n_qgroups, k, qi)) return;      // no barriers below: a wave may leave on its own
+    const QDev Q = B.q[qi];
+    const int64_t kq = shifted_k(M, Q, k);
+    const int row = lane & 15, g = lane >> 4;
+    const int nb = M.nb, no = M.no;
+    const double *pa[NT];
+    const double *pb[NT];
+    bool ok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = t * 16 + row;
+        ok[t] = n < M.nbw;
+        pa[t] = M.c_k + 2 * ((k * no) * nb + M.lo + (ok[t] ? n : 0));
+        pb[t] = Q.c_kq + 2 * ((kq * no) * nb + M.lo + (ok[t] ? n : 0));
+    }
+    SplitAcc acc[NT][NT];
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < NT; ++tm) acc[tn][tm].re = acc[tn][tm].re_c = acc[tn][tm].im = acc[tn][tm].im_c = flt4{0.f, 0.f, 0.f, 0.f};
+    constexpr int D = pw_split_depth(NT);
+    double2 av[D][NT][4], bv[D][NT][4];
+    // unconditional loads, clamped to the last orbital and zeroed past it (as in contract_pw_kernel)
+    auto fetch = [&](int d, int o0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = o0 + 4 * g + i;
+            const int64_t off = 2 * (int64_t)min(o, no - 1) * nb;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bool use = o < no && ok[t];
+                const double2 a = *reinterpret_cast<const double2 *>(pa[t] + off);
+                const double2 b = *reinterpret_cast<const double2 *>(pb[t] + off);
+                av[d][t][i] = use ? a : double2{0.0, 0.0};
+                bv[d][t][i] = use ? b : double2{0.0, 0.0};
+            }
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) fetch(d, 16 * d);
+    for (int o0 = 0; o0 < no; o0 += 16 * D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u32x4 ah[NT], al[NT], bh[NT], bl[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                split_op<FP16>(av[d][t], ah[t], al[t]);
+                split_op<FP16>(bv[d][t], bh[t], bl[t]);
+            }
+            fetch(d, o0 + 16 * (d + D));
+#pragma unroll
+            for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+                for (int tm = 0; tm < NT; ++tm) split_step<FP16>(acc[tn][tm], ah[tn], al[tn], bh[tm], bl[tm]);
+        }
+    }
+    // accumulator element v of this lane is D[4 g + v][row]: band n = tn*16 + 4g + v, m = tm*16 + row
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < NT; ++tm)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int nn = tn * 16 + 4 * g + v, mm = tm * 16 + row;
+                if (nn < M.nbw && mm < M.nbw) Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = split_abs2<FP16>(acc[tn][tm], v);
+            }
+}
+
 // Fused launch over the (instance, q) items of a batch: workgroup -> item from a table.
 __global__ __launch_bounds__(64) void contract_batch_kernel(const BatchItemDev *__restrict__ items,
                                                             const int32_t *__restrict__ block_item)
@@ -401,19 +501,25 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     if (mesh.no > kMaxOrbSmall) {
-        // large (plane-wave) bases: one workgroup per (k, group of up to kPwQ q), FP64 in every precision
+        // large (plane-wave) bases: one workgroup per (k, group of up to kPwQ q)
         if (mesh.nbw > 32) return hipErrorInvalidValue;
         const int gq = nq < kPwQ ? nq : kPwQ;           // q (waves) per workgroup
         const int ng = (nq + gq - 1) / gq;
         const int64_t k_per_xcd = (mesh.nk + kXcd - 1) / kXcd;
         const int64_t nblk = k_per_xcd * kXcd * ng;
         if (nblk >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-        if (mesh.nbw > 16)
-            hipLaunchKernelGGL(contract_pw_kernel<2>, dim3((unsigned)nblk), dim3(64 * gq), 0, s, mesh, batch,
-                               nq, ng);
-        else
-            hipLaunchKernelGGL(contract_pw_kernel<1>, dim3((unsigned)nblk), dim3(64 * gq), 0, s, mesh, batch,
-                               nq, ng);
+        const dim3 grid((unsigned)nblk), block(64 * gq);
+        const bool two = mesh.nbw > 16;
+        if (precision == 1) {
+            if (two) hipLaunchKernelGGL((contract_pw_split_kernel<2, false>), grid, block, 0, s, mesh, batch, nq, ng);
+            else hipLaunchKernelGGL((contract_pw_split_kernel<1, false>), grid, block, 0, s, mesh, batch, nq, ng);
+        } else if (precision == 2) {
+            if (two) hipLaunchKernelGGL((contract_pw_split_kernel<2, true>), grid, block, 0, s, mesh, batch, nq, ng);
+            else hipLaunchKernelGGL((contract_pw_split_kernel<1, true>), grid, block, 0, s, mesh, batch, nq, ng);
+        } else {
+            if (two) hipLaunchKernelGGL(contract_pw_kernel<2>, grid, block, 0, s, mesh, batch, nq, ng);
+            else hipLaunchKernelGGL(contract_pw_kernel<1>, grid, block, 0, s, mesh, batch, nq, ng);
+        }
         return hipGetLastError();
     }
     const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;

@@ -34,7 +34,7 @@ def _plan(wl, **kw):
     ck = None if wl.c_k is None else torch.from_numpy(np.ascontiguousarray(wl.c_k)).to(dev)
     lo, hi = wl.window()
     plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
-                        cma=wl.cma, form=kw.get("form", wl.form))
+                        cma=wl.cma, form=kw.get("form", wl.form), precision=kw.get("precision", 0))
     qs = []
     for q in wl.qs:
         if q.shift is not None:
@@ -355,16 +355,49 @@ def test_plane_wave_matrix_elements(n_pw, nb, nq):
         assert abs(together[i] - ref) <= TOL * abs(ref), (i, together[i], ref)
 
 
-def test_plane_wave_dynamic_chi0():
-    """chi0 with plane-wave matrix elements (300 plane waves, 6 bands) against the oracle."""
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("n_pw,nb,nq", [(1001, 24, 2), (998, 10, 11)])
+def test_plane_wave_matrix_elements_split_precision(precision, n_pw, nb, nq):
+    """Split-product plane-wave contraction (BF16x3 = 1, FP16x3 = 2 on the 16x16x32 MFMAs) against
+    numpy's FP64 |M|^2, element by element.  With S = sum_o (|ar|+|ai|)(|br|+|bi|) over the basis,
+    each real product is exact to about 2^-16 (BF16: hi and lo keep 8 bits each, the dropped lo*lo
+    term is 2^-18 of the product) or 2^-21 (FP16) of its magnitude, so |dM| <= c S with c = 2^-14
+    or 2^-19 (a factor 4 left for the FP32 accumulation), and |dW| <= 2|M| c S + (c S)^2."""
+    torch = _torch()
+    wl = synth.plane_wave_workload((4, 3, 3), n_pw, nb, nq=nq, nw=4)
+    plan, qs = _plan(wl, precision=precision)
+    c_eps = 2.0 ** -14 if precision == 1 else 2.0 ** -19
+    _say("plane-wave split matrix elements", precision, n_pw, nb, nq)
+    idx = np.arange(wl.n_k).reshape(wl.nk)
+    a = np.abs(wl.c_k.real) + np.abs(wl.c_k.imag)
+    worst = 0.0
+    for i, q in enumerate(wl.qs):
+        W = plan.matrix_elements(qs[i]).cpu().numpy()
+        s = q.shift
+        kq = np.roll(idx, shift=(-s[0], -s[1], -s[2]), axis=(0, 1, 2)).ravel()
+        M = np.einsum("kon,kom->nmk", wl.c_k.conj(), wl.c_k[kq])
+        e = c_eps * np.einsum("kon,kom->nmk", a, a[kq])
+        bound = 2 * np.abs(M) * e + e * e
+        ratio = np.max(np.abs(W - np.abs(M) ** 2) / bound)
+        worst = max(worst, ratio)
+    _say(f"largest |dW| / bound {worst:.3f}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_plane_wave_dynamic_chi0(precision):
+    """chi0 with plane-wave matrix elements (300 plane waves, 6 bands) against the oracle: FP64
+    within the FP64 bar, the split forms within the mixed-form bar."""
     torch = _torch()
     wl = synth.plane_wave_workload((4, 4, 3), 300, 6, nq=2, nw=40)
-    plan, qs = _plan(wl)
-    _say("plane-wave dynamic chi0")
+    plan, qs = _plan(wl, precision=precision)
+    _say("plane-wave dynamic chi0, precision", precision)
     got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()
     for i in range(len(wl.qs)):
         ref = oracle.chi0(wl, i)
-        assert _relerr(got[i], ref) <= TOL
+        err = _relerr(got[i], ref)
+        _say(f"q {i}: per-result error {err:.2e}")
+        assert err <= (TOL if precision == 0 else 1e-5)
 
 
 def _host_carving_lib():
