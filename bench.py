@@ -355,24 +355,28 @@ def bench_pw(args):
     del a_h, b, m, w_lib
 
     # split-precision forms of the same step: time, matrix-element and chi0 errors against this run's
-    # FP64 result, and the roofline of their contraction kernel (HBM: the FP64 coefficients are read
-    # as they are; the matrix cores do 24 flops per band pair and basis function, two real GEMMs of
-    # doubled depth with three products each)
+    # FP64 result, and the roofline of their contraction (HBM).  With 16 q given by mesh shifts the
+    # library splits the window's coefficients once per launch into packed 8-byte operands (read 16
+    # bytes, write 8 per coefficient) and the contraction kernel reads those, at every k once and at
+    # every k+q once per q; the matrix cores do 24 flops per band pair and basis function (two real
+    # GEMMs of doubled depth, three products each).
+    packed_bytes = (n_pw * nbw * (16.0 + 8.0 + 8.0 * (1 + q_per_launch)) + nbw * nbw * 8.0 * q_per_launch) * wl.n_k
     ref64 = out.clone()
     mixed = {}
     for prec, name in ((1, "bf16x3"), (2, "fp16x3")):
         mplan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
                              precision=prec)
         mout = torch.empty_like(out)
+        mws = mplan.workspace(len(qs), 1)      # with room for the packed split operands
         for _ in range(max(1, args.warmup)):
-            mplan.static(qs, workspace=ws, out=mout)
+            mplan.static(qs, workspace=mws, out=mout)
         torch.cuda.synchronize()
         mplan.profile(True)
         mplan.read_profile()
         m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         m0.record(stream)
         for _ in range(args.steps):
-            mplan.static(qs, workspace=ws, out=mout)
+            mplan.static(qs, workspace=mws, out=mout)
         m1.record(stream)
         torch.cuda.synchronize()
         mms = m0.elapsed_time(m1) / args.steps
@@ -384,7 +388,7 @@ def bench_pw(args):
         torch.cuda.synchronize()
         w_err = float((w_split - w_ours).abs().max() / w_ours.abs().max())
         chi_err = float(((mout - ref64).abs() / ref64.abs()).max())
-        hbm = bytes_launch / (m_avg * 1e-3) / 1e9
+        hbm = packed_bytes / (m_avg * 1e-3) / 1e9
         split_flops = 24.0 * n_pw * nbw * nbw * wl.n_k * q_per_launch
         mixed[name] = {"ms_per_step": round(mms, 3), "speedup_vs_fp64": round(ms / mms, 3),
                        "contract_ms_per_launch": round(m_avg, 3),
@@ -392,12 +396,12 @@ def bench_pw(args):
                        "max_rel_err_of_W_vs_fp64": w_err, "max_rel_err_of_chi0_vs_fp64": chi_err,
                        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
                                     "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
-                                    "kernel": "contract_pw_split_kernel",
-                                    "algorithmic_bytes_per_launch": bytes_launch,
+                                    "kernel": "pack_split_kernel + contract_pw_packed_kernel",
+                                    "algorithmic_bytes_per_launch": packed_bytes,
                                     "mfma_tflops": round(split_flops / (m_avg * 1e-3) / 1e12, 1)}}
         log(f"{name}: {mms:.2f} ms/step, contraction {m_avg:.3f} ms/launch ({hbm:.0f} GB/s), "
             f"W err {w_err:.2e}, chi0 err {chi_err:.2e}")
-        del mplan, mout, w_split
+        del mplan, mout, mws, w_split
     result["mixed"] = mixed
 
     if not args.no_cpu_baseline:

@@ -136,7 +136,11 @@ chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *desc, const double *eps
                       const double *c_k, void *hip_stream);
 
 /* Device workspace (bytes) needed by chi0_static / chi0_dynamic for nq q-points and nw
- * frequencies (nw = 1 for the static call). */
+ * frequencies (nw = 1 for the static call).  It holds the matrix elements and partial sums of
+ * the q of one launch sequence (batch_hint) and, for a split-precision plan with a basis above 64
+ * whose launches take 3 or more q, the eigenvectors of the band window split once into 16-bit
+ * high and low parts (8 bytes per coefficient): launches whose q are all mesh shifts read those
+ * instead of the FP64 coefficients. */
 chi0_status chi0_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, size_t *bytes);
 
 /* Static chi0(q, 0) (Sec. III uses Eq. (1) at w = 0, where Im vanishes).

@@ -208,12 +208,14 @@ int n_blocks_pair(const chi0_plan_s *p)
 }
 
 struct Layout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, count_off, flag_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, pack_off, pack_bytes, count_off, flag_off, total;
     int qbatch;
 };
 
-// qcap > 0 caps the q-points per launch sequence below the plan's own (the no-allocation call)
-Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0)
+// qcap > 0 caps the q-points per launch sequence below the plan's own (the no-allocation call);
+// packed: room for the split operands of a split-precision plane-wave plan whose launches take
+// at least kPackMinQ q (not in the no-allocation call, whose scratch is too small for them).
+Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0, bool packed = true)
 {
     Layout L;
     L.qbatch = std::min(nq, qcap > 0 ? std::min(qcap, p->qbatch) : p->qbatch);
@@ -224,10 +226,20 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0)
                                                            (size_t)n_blocks_pair(p) * npairs));
     L.w_off = 0;
     L.part_off = L.w_bytes_per_q * L.qbatch;
-    L.count_off = L.part_off + L.part_bytes_per_q * L.qbatch;
+    L.pack_off = L.part_off + L.part_bytes_per_q * L.qbatch;
+    L.pack_bytes = packed && L.qbatch >= kPackMinQ && !p->d.cma && p->d.precision != 0 && p->mesh.no > kMaxOrbSmall
+                       ? align_up(pack_bytes(p->mesh))
+                       : 0;
+    L.count_off = L.pack_off + L.pack_bytes;
     L.flag_off = L.count_off + 128;       // census counters (48 bytes), then the scan verdict
     L.total = L.count_off + kAlign;
     return L;
+}
+
+// The split-operand region of a call's workspace, not yet filled.
+PackState pack_state(void *ws, const Layout &L)
+{
+    return PackState{L.pack_bytes ? static_cast<char *>(ws) + L.pack_off : nullptr, false};
 }
 
 unsigned *scan_flag(void *ws, const Layout &L)
@@ -644,13 +656,15 @@ chi0_status chi0_static(chi0_plan_t p, int32_t nq, const chi0_q *qs, void *ws, s
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
+    PackState pk = pack_state(ws, L);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, nqb, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, nqb, nblk, partial, p->stream); })) !=
             hipSuccess)
@@ -677,13 +691,15 @@ chi0_status chi0_static_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, void 
     const int npairs = p->mesh.nbw * p->mesh.nbw;
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
+    PackState pk = pack_state(ws, L);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, nqb, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         if ((e = timed(p, 1, [&] { return launch_tetra_static_pairs(p->mesh, B, nqb, nblk, partial, p->stream); })) !=
             hipSuccess)
@@ -711,20 +727,21 @@ chi0_status dynamic_run(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
     if (st) return st;
     if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
     const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
-    const Layout L = layout(p, nq, 2 * nwc_max, qcap);
+    const Layout L = layout(p, nq, 2 * nwc_max, qcap, !no_alloc);
     if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
     if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
+    PackState pk = pack_state(ws, L);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
         fill_batch(p, qs, q0, nqb, ws, L, B);
         hipError_t e;
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); }, no_alloc)) !=
-                hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, nqb, p->d.precision, &pk, p->stream);
+                          }, no_alloc)) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
@@ -754,8 +771,8 @@ chi0_status dynamic_scratch(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
     if (nq < 1 || nw < 1) return fail(p, CHI0_E_INVALID_ARG, "nq and nw must be >= 1");
     const int nvals = 2 * std::min(nw, kMaxOmegaPerLaunch);
     int qcap = p->qbatch;
-    while (qcap > 1 && layout(p, nq, nvals, qcap).total > scratch_bytes) --qcap;
-    if (layout(p, nq, nvals, qcap).total > scratch_bytes)
+    while (qcap > 1 && layout(p, nq, nvals, qcap, false).total > scratch_bytes) --qcap;
+    if (layout(p, nq, nvals, qcap, false).total > scratch_bytes)
         return fail(p, CHI0_E_WORKSPACE, "the no-allocation call's fixed scratch cannot hold the workspace of one q of "
                                          "this plan (use chi0_dynamic with a caller workspace)");
     return dynamic_run(p, nq, qs, nw, omega, scratch, scratch_bytes, chi, qcap, true);
@@ -814,12 +831,14 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
     Layout Lw = {};   // W of the batch sits at the start of the workspace, as for chi0_dynamic
     Lw.w_off = L.w_off;
     Lw.w_bytes_per_q = L.w_bytes_per_q;
+    PackState pk = pack_state(ws, Lw);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
         BatchDev B;
         fill_batch(p, qs, q0, nqb, ws, Lw, B);
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, nqb, p->d.precision, p->stream); })) != hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, nqb, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         for (int w0 = 0; w0 < L.n_all; w0 += kMaxOmegaIm) {
             const int nwc = std::min(kMaxOmegaIm, L.n_all - w0);
@@ -858,13 +877,15 @@ chi0_status chi0_static_group(chi0_plan_t p, int32_t nq, int32_t n_group, const 
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
+    PackState pk = pack_state(ws, L);
     for (const GroupLaunch &G : group_launches(nq, n_group, p->qbatch)) {
         BatchDev B;
         fill_batch(p, qs, G.e0, G.ne, ws, L, B);
         const int per_group = G.ne / G.ng;
         hipError_t e;
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, G.ne, p->d.precision, p->stream); })) != hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, G.ne, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         if ((e = timed(p, 1, [&] { return launch_tetra_static(p->mesh, B, G.ne, nblk, partial, p->stream); })) !=
             hipSuccess)
@@ -897,13 +918,15 @@ chi0_status chi0_dynamic_group(chi0_plan_t p, int32_t nq, int32_t n_group, const
     const int nblk = n_blocks(p);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     const double scale = prefactor(p);
+    PackState pk = pack_state(ws, L);
     for (const GroupLaunch &G : group_launches(nq, n_group, p->qbatch)) {
         BatchDev B;
         fill_batch(p, qs, G.e0, G.ne, ws, L, B);
         const int per_group = G.ne / G.ng;
         hipError_t e;
-        if (!p->d.cma &&
-            (e = timed(p, 0, [&] { return launch_contract(p->mesh, B, G.ne, p->d.precision, p->stream); })) != hipSuccess)
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, G.ne, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
             return device_fail(p, e, "matrix-element kernel");
         for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
             const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
@@ -935,7 +958,7 @@ chi0_status chi0_matrix_elements(chi0_plan_t p, const chi0_q *q, double *W)
     Layout L = layout(p, 1, 1);
     BatchDev B;
     fill_batch(p, q, 0, 1, W, L, B);
-    hipError_t e = launch_contract(p->mesh, B, 1, p->d.precision, p->stream);
+    hipError_t e = launch_contract(p->mesh, B, 1, p->d.precision, nullptr, p->stream);
     if (e != hipSuccess) return device_fail(p, e, "matrix-element kernel");
     return CHI0_OK;
 }

@@ -75,7 +75,18 @@ hipError_t launch_reduce_batch(const BatchItemDev *items, const int32_t *block_i
 
 // K_A: W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for nq q-points of a batch.
 // precision 0: FP64 MFMA; 1: BF16 hi+lo split MFMA; 2: FP16 hi+lo split MFMA (FP32 accumulate).
-hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s);
+// Split operands of the plan's eigenvectors in the workspace (pack_bytes(mesh)); ptr null: none.
+// A split-precision plane-wave launch of at least kPackMinQ q, all given by mesh shifts, fills them
+// unless valid is set (an earlier launch of the same call did) and reads them instead of the FP64
+// eigenvectors.
+struct PackState {
+    void *ptr;
+    bool valid;
+};
+hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, PackState *pack,
+                           hipStream_t s);
+constexpr int kPackMinQ = 3;
+size_t pack_bytes(const MeshDev &mesh);
 
 // K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
 hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,

@@ -472,6 +472,117 @@ __global__ __launch_bounds__(64 * kPwQ) void contract_pw_split_kernel(MeshDev M,
             }
 }
 
+// Packed split operands.  When every q of a launch is a mesh shift, all its k+q operands are rows
+// of the plan's own eigenvector array, so the split is done once per launch: pack_split_kernel
+// writes, for every (k, block of 4 orbitals, band n of the window), the 32 bytes a lane loads for
+// one MFMA step (hi of [re o..o+3, im o..o+3], then lo), and contract_pw_packed_kernel reads them
+// for both operands: 8 bytes per coefficient instead of 16, and no conversion in the loop.
+constexpr int kPackThreads = 256;
+
+template <bool FP16>
+__global__ __launch_bounds__(kPackThreads) void pack_split_kernel(MeshDev M, u32x4 *__restrict__ pack)
+{
+    const int nb4 = (M.no + 3) / 4;
+    const int64_t total = M.nk * (int64_t)nb4 * M.nbw;
+    for (int64_t e = (int64_t)blockIdx.x * kPackThreads + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kPackThreads) {
+        const int n = (int)(e % M.nbw);
+        const int64_t t = e / M.nbw;
+        const int blk = (int)(t % nb4);
+        const int64_t k = t / nb4;
+        double2 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = 4 * blk + i;
+            v[i] = o < M.no ? *reinterpret_cast<const double2 *>(M.c_k + 2 * ((k * M.no + o) * M.nb + M.lo + n))
+                            : double2{0.0, 0.0};
+        }
+        u32x4 hi, lo;
+        split_op<FP16>(v, hi, lo);
+        pack[2 * e] = hi;
+        pack[2 * e + 1] = lo;
+    }
+}
+
+constexpr int pw_packed_depth(int nt) { return nt == 1 ? 4 : 2; }
+
+template <int NT, bool FP16>
+__global__ __launch_bounds__(64 * kPwQ) void contract_pw_packed_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups,
+                                                                        const u32x4 *__restrict__ pack)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t k;
+    int qi;
+    if (!pw_item(M, nq, n_qgroups, k, qi)) return;      // no barriers below: a wave may leave on its own
+    const QDev Q = B.q[qi];
+    const int64_t kq = shifted_k(M, Q, k);
+    const int row = lane & 15, g = lane >> 4;
+    const int nb4 = (M.no + 3) / 4;
+    const int nsteps = (nb4 + 3) / 4;      // steps of 16 orbitals (4 blocks of 4)
+    const u32x4 *pa[NT];
+    const u32x4 *pb[NT];
+    bool ok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = t * 16 + row;
+        ok[t] = n < M.nbw;
+        pa[t] = pack + 2 * ((k * nb4) * M.nbw + (ok[t] ? n : 0));
+        pb[t] = pack + 2 * ((kq * nb4) * M.nbw + (ok[t] ? n : 0));
+    }
+    SplitAcc acc[NT][NT];
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < NT; ++tm) acc[tn][tm].re = acc[tn][tm].re_c = acc[tn][tm].im = acc[tn][tm].im_c = flt4{0.f, 0.f, 0.f, 0.f};
+    constexpr int D = pw_packed_depth(NT);
+    u32x4 ah[D][NT], al[D][NT], bh[D][NT], bl[D][NT];
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    // unconditional loads, clamped to the last block and zeroed past it
+    auto fetch = [&](int d, int step) {
+        const int blk = 4 * step + g;
+        const int64_t off = 2 * (int64_t)min(blk, nb4 - 1) * M.nbw;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bool use = blk < nb4 && ok[t];
+            const u32x4 a0 = pa[t][off], a1 = pa[t][off + 1];
+            const u32x4 b0 = pb[t][off], b1 = pb[t][off + 1];
+            ah[d][t] = use ? a0 : zero;
+            al[d][t] = use ? a1 : zero;
+            bh[d][t] = use ? b0 : zero;
+            bl[d][t] = use ? b1 : zero;
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) fetch(d, d);
+    for (int s0 = 0; s0 < nsteps; s0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            u32x4 xh[NT], xl[NT], yh[NT], yl[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                xh[t] = ah[d][t];
+                xl[t] = al[d][t];
+                yh[t] = bh[d][t];
+                yl[t] = bl[d][t];
+            }
+            fetch(d, s0 + d + D);
+#pragma unroll
+            for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+                for (int tm = 0; tm < NT; ++tm) split_step<FP16>(acc[tn][tm], xh[tn], xl[tn], yh[tm], yl[tm]);
+        }
+    }
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < NT; ++tm)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int nn = tn * 16 + 4 * g + v, mm = tm * 16 + row;
+                if (nn < M.nbw && mm < M.nbw) Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = split_abs2<FP16>(acc[tn][tm], v);
+            }
+}
+
 // Fused launch over the (instance, q) items of a batch: workgroup -> item from a table.
 __global__ __launch_bounds__(64) void contract_batch_kernel(const BatchItemDev *__restrict__ items,
                                                             const int32_t *__restrict__ block_item)
@@ -497,7 +608,13 @@ hipError_t launch_contract_batch(const BatchItemDev *items, const int32_t *block
     return hipGetLastError();
 }
 
-hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, hipStream_t s)
+size_t pack_bytes(const MeshDev &mesh)
+{
+    return (size_t)mesh.nk * (size_t)((mesh.no + 3) / 4) * (size_t)mesh.nbw * 2 * sizeof(u32x4);
+}
+
+hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, int precision, PackState *pack,
+                           hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
     if (mesh.no > kMaxOrbSmall) {
@@ -510,6 +627,25 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
         if (nblk >= (int64_t(1) << 31)) return hipErrorInvalidValue;
         const dim3 grid((unsigned)nblk), block(64 * gq);
         const bool two = mesh.nbw > 16;
+        bool shifts = true;
+        for (int i = 0; i < nq; ++i) shifts = shifts && !batch.q[i].explicit_kq;
+        if (precision != 0 && pack && pack->ptr && shifts && nq >= kPackMinQ) {
+            u32x4 *pk = static_cast<u32x4 *>(pack->ptr);
+            const int64_t total = mesh.nk * (int64_t)((mesh.no + 3) / 4) * mesh.nbw;
+            const unsigned pblk = (unsigned)std::min<int64_t>((total + kPackThreads - 1) / kPackThreads, 65536);
+            const bool fill = !pack->valid;
+            pack->valid = true;
+            if (precision == 1) {
+                if (fill) hipLaunchKernelGGL(pack_split_kernel<false>, dim3(pblk), dim3(kPackThreads), 0, s, mesh, pk);
+                if (two) hipLaunchKernelGGL((contract_pw_packed_kernel<2, false>), grid, block, 0, s, mesh, batch, nq, ng, pk);
+                else hipLaunchKernelGGL((contract_pw_packed_kernel<1, false>), grid, block, 0, s, mesh, batch, nq, ng, pk);
+            } else {
+                if (fill) hipLaunchKernelGGL(pack_split_kernel<true>, dim3(pblk), dim3(kPackThreads), 0, s, mesh, pk);
+                if (two) hipLaunchKernelGGL((contract_pw_packed_kernel<2, true>), grid, block, 0, s, mesh, batch, nq, ng, pk);
+                else hipLaunchKernelGGL((contract_pw_packed_kernel<1, true>), grid, block, 0, s, mesh, batch, nq, ng, pk);
+            }
+            return hipGetLastError();
+        }
         if (precision == 1) {
             if (two) hipLaunchKernelGGL((contract_pw_split_kernel<2, false>), grid, block, 0, s, mesh, batch, nq, ng);
             else hipLaunchKernelGGL((contract_pw_split_kernel<1, false>), grid, block, 0, s, mesh, batch, nq, ng);

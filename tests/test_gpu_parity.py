@@ -34,7 +34,8 @@ def _plan(wl, **kw):
     ck = None if wl.c_k is None else torch.from_numpy(np.ascontiguousarray(wl.c_k)).to(dev)
     lo, hi = wl.window()
     plan = lib.Chi0Plan(wl.nk, eps, ck, mu=wl.mu, spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi,
-                        cma=wl.cma, form=kw.get("form", wl.form), precision=kw.get("precision", 0))
+                        cma=wl.cma, form=kw.get("form", wl.form), precision=kw.get("precision", 0),
+                        batch_hint=kw.get("batch_hint", 0))
     qs = []
     for q in wl.qs:
         if q.shift is not None:
@@ -382,6 +383,31 @@ def test_plane_wave_matrix_elements_split_precision(precision, n_pw, nb, nq):
         worst = max(worst, ratio)
     _say(f"largest |dW| / bound {worst:.3f}")
     assert worst <= 1.0
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("n_pw,nb", [(1001, 24), (998, 10)])
+def test_plane_wave_packed_operands(precision, n_pw, nb):
+    """A split-precision launch of 3 or more q given by mesh shifts splits the eigenvectors once into
+    packed operands and reads those; a launch of fewer q splits them as it reads.  Both give the same
+    operands and MFMA sequence, so the pair-resolved static chi0 of 7 q in one launch, of launches of
+    3, 3 and 1 q (the packed operands filled once and reused) and of one q per call must agree to
+    the rounding of the FP64 sums, and all within the mixed-form bar of the oracle."""
+    torch = _torch()
+    wl = synth.plane_wave_workload((4, 3, 3), n_pw, nb, nq=7, nw=4)
+    plan, qs = _plan(wl, precision=precision)
+    plan3, _ = _plan(wl, precision=precision, batch_hint=3)
+    _say("plane-wave packed operands", precision, n_pw, nb)
+    together = plan.static_pairs(qs).cpu().numpy()
+    in_threes = plan3.static_pairs(qs).cpu().numpy()
+    alone = np.stack([plan.static_pairs([q]).cpu().numpy()[0] for q in qs])
+    scale = np.max(np.abs(alone))
+    assert np.max(np.abs(together - alone)) <= 1e-13 * scale
+    assert np.max(np.abs(in_threes - alone)) <= 1e-13 * scale
+    for i in range(len(qs)):
+        ref = oracle.chi0(wl, i, omega=np.zeros(1))[0].real
+        got = together[i].sum()
+        assert abs(got - ref) <= 1e-5 * abs(ref), (i, got, ref)
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
