@@ -832,6 +832,23 @@ def main():
                                    "metric": "per result: |d| / max(|ref|, 1e-3 max_w |ref|)"}
         log(f"oracle sample {dt:.1f}s (median of 3, {cores['threads']} threads), "
             f"max rel err {result['parity_sample']['max_rel_err_vs_oracle']:.2e}")
+        # The second op count: the oracle's own tally of floating-point operations on its sample
+        # (weights in chi0_oracle.c), per active unit and frequency, times the launch's active units
+        # and frequencies.  The oracle evaluates every (final tetrahedron, frequency) pair by full
+        # divided differences with complex logarithms and no far series, so this figure measures
+        # how much work the kernel's formulation saves, not how well it uses the ALUs; `frac`
+        # above is the census count.
+        o_ops, o_units = oracle.last_count()
+        per_unit_w = o_ops / max(1, o_units * len(sample_w))
+        o_flops_launch = per_unit_w * census["active_units"] * nw / launches_per_step
+        o_rate = o_flops_launch / (avg_ms * 1e-3) / 1e12
+        roofline["oracle_count"] = {"flops_per_active_unit_and_w": round(per_unit_w, 1),
+                                    "sample_active_units": o_units, "flops_per_launch": o_flops_launch,
+                                    "achieved": round(o_rate, 1), "frac": round(o_rate / FP64_PEAK_TFLOPS, 2),
+                                    "note": "oracle formulation (full divided differences for every pair); "
+                                            "frac above uses the census count"}
+        log(f"oracle op count: {per_unit_w:.0f} flops per active unit and w; "
+            f"{o_rate:.0f} TFLOP/s oracle-equivalent ({o_rate / FP64_PEAK_TFLOPS:.1f}x the FP64 peak)")
 
     if not args.no_mixed:
         # mixed forms: split BF16 / FP16 MFMA matrix elements, FP32 weights with the FP64 near branch

@@ -56,6 +56,9 @@ def _load():
         lib.chi0_oracle_list.restype = i
         lib.chi0_oracle_z.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, d, d, i, i, i, i, dp, d, i, dp]
         lib.chi0_oracle_z.restype = i
+        ull = ctypes.POINTER(ctypes.c_ulonglong)
+        lib.chi0_oracle_last_count.argtypes = [ull, ull]
+        lib.chi0_oracle_last_count.restype = None
         lib.chi0_oracle_W.argtypes = [i, i, i, i, i, dp, dp, dp, dp, i, i, i, i, i, dp]
         lib.chi0_oracle_W.restype = i
         lib.chi0_oracle_tet_corners.argtypes = [i, i, i, ll, i, ctypes.POINTER(ctypes.c_longlong)]
@@ -217,6 +220,16 @@ def chi0(wl, q_index: int, omega=None, cells=None, nthreads: int = 0, form: Opti
                     shift=q.shift if q.shift is not None else (0, 0, 0), mu=wl.mu,
                     spin_factor=wl.spin_factor, band_lo=lo, band_hi=hi, cma=wl.cma,
                     form=wl.form if form is None else form, cells=cells, nthreads=nthreads)
+
+
+def last_count():
+    """(operations, active units) of the last chi0 / chi0_raw / chi0_z_raw call: the oracle's own
+    floating-point operation tally (weights in chi0_oracle.c) and the (mesh tetrahedron, band pair)
+    units with a non-empty carved region."""
+    lib = _load()
+    ops, units = ctypes.c_ulonglong(0), ctypes.c_ulonglong(0)
+    lib.chi0_oracle_last_count(ctypes.byref(ops), ctypes.byref(units))
+    return int(ops.value), int(units.value)
 
 
 def chi0_pairs(wl, q_index: int, omega=None, nthreads: int = 0, form: Optional[int] = None) -> np.ndarray:

@@ -56,6 +56,17 @@ typedef double complex cplx;
 #define THETA 0.5
 #define TAYLOR_MAX_TERMS 400
 
+/* Operation count of the last mesh evaluation (for the benchmark's op-count figure; it changes
+ * no value).  Every floating-point operation of the carving and of the weight evaluation is
+ * tallied in a per-thread counter with these weights: real add, subtract, multiply, divide 1;
+ * complex add 2, complex multiply 6, complex divide 11; modulus 5; complex logarithm 87 (the
+ * modulus plus two real transcendental functions, log and arg, at 41 each).  Units (mesh
+ * tetrahedron, band pair) whose carved regions are not empty are counted beside it. */
+enum { OP_CADD = 2, OP_CMUL = 6, OP_CDIV = 11, OP_CABS = 5, OP_CLOG = 87 };
+static _Thread_local unsigned long long t_ops, t_units;
+static unsigned long long g_ops, g_units;
+#define OPS(n) (t_ops += (unsigned long long)(n))
+
 /* ------------------------------------------------------------------------- */
 /* The function h(x) = (w-x)^3 Log(w-x+i0) and its derivatives               */
 /* ------------------------------------------------------------------------- */
@@ -69,6 +80,7 @@ static cplx log_upper(cplx u) { return clog(u); }
 /* u^k for a small integer k (negative k: 1/u^|k|), by repeated multiplication */
 static cplx cpowi(cplx u, int k)
 {
+    OPS((k < 0 ? -k : k) * OP_CMUL + (k < 0 ? OP_CDIV : 0));
     cplx r = 1.0;
     for (int i = 0; i < (k < 0 ? -k : k); ++i) r *= u;
     return k < 0 ? 1.0 / r : r;
@@ -89,9 +101,11 @@ static cplx hder_fact(int n, cplx u)
     }
     if (n >= 4) {
         double nn = (double)n;
+        OPS(6 + 2 + OP_CDIV);
         return 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0) * cpowi(u, n - 3));
     }
     cplx L = log_upper(u);
+    OPS(OP_CLOG + (n == 0 ? 3 * OP_CMUL : n == 1 ? 3 * OP_CMUL + 2 + OP_CADD + 2 : n == 2 ? OP_CMUL + 6 + OP_CADD : 7));
     switch (n) {
     case 0: return u * u * u * L;
     case 1: return -(3.0 * u * u * L + u * u);
@@ -112,11 +126,13 @@ static cplx dd_taylor(const double *x, int i, int j, double c, cplx z)
         y[v] = (x[i + v] - c) / u;
         if (cabs(y[v]) > rho) rho = cabs(y[v]);
     }
+    OPS(1 + (p + 1) * (1 + OP_CDIV + OP_CABS));
     if (rho == 0.0) return hder_fact(p, u);      /* all nodes equal: h^(p)(c)/p! */
     /* number of terms: the bound C(m+p,p) rho^m falls below 1e-18 (at least 4 terms) */
     int M = 0;
     for (double b = 1.0; M < TAYLOR_MAX_TERMS && (M < 4 || b > 1e-18); ++M)
         b *= (double)(M + p + 1) / (double)(M + 1) * rho;
+    OPS(5 * M + (p + 1) * M * (OP_CMUL + OP_CADD));
     /* H[m] = H_m(y) of the scaled offsets, built up one variable at a time */
     cplx H[TAYLOR_MAX_TERMS + 1];
     H[0] = 1.0;
@@ -131,8 +147,10 @@ static cplx dd_taylor(const double *x, int i, int j, double c, cplx z)
         int n = p + m;
         if (n >= 4) {
             double nn = (double)n;
+            OPS(7 + 2 + OP_CMUL + OP_CADD);
             s += 6.0 / (nn * (nn - 1.0) * (nn - 2.0) * (nn - 3.0)) * up * H[m];
         } else {
+            OPS(2 * OP_CMUL + OP_CADD);
             s += hder_fact(n, u) * cpowi(u, m) * H[m];
         }
     }
@@ -150,10 +168,12 @@ static cplx dd_entry(const double *x, int i, int j, cplx z, cplx tab[5][5], int 
         double span = x[j] - x[i];
         double di = cabs(z - x[i]), dj = cabs(z - x[j]);
         double far = di > dj ? di : dj;
+        OPS(1 + 2 * (1 + OP_CABS) + 1);
         if (span <= THETA * far) {
             v = dd_taylor(x, i, j, di >= dj ? x[i] : x[j], z);
         } else {
             v = (dd_entry(x, i + 1, j, z, tab, done) - dd_entry(x, i, j - 1, z, tab, done)) / span;
+            OPS(OP_CADD + 2);
         }
     }
     tab[i][j] = v;
@@ -198,6 +218,7 @@ typedef struct { double b[4][4]; } btet;
 
 static double det4(const double m[4][4])
 {
+    OPS(4 + 3 * (1 + 2 * 4) + 2 * (1 + 2 * 3) + (1 + 2 * 2));   /* pivot products, eliminations */
     double a[4][4];
     memcpy(a, m, sizeof a);
     double det = 1.0;
@@ -227,6 +248,7 @@ static void set_vertex(btet *t, int v, const double *p) { memcpy(t->b[v], p, 4 *
 /* point on the edge from vertex p (f<0) to vertex q (f>=0) where the linear f vanishes */
 static void cut_point(const btet *t, int p, int q, const double *fv, double *out)
 {
+    OPS(2 + 4 * 3);
     double s = fv[p] / (fv[p] - fv[q]);
     for (int i = 0; i < 4; ++i) out[i] = t->b[p][i] + s * (t->b[q][i] - t->b[p][i]);
 }
@@ -237,6 +259,7 @@ static int clip_negative(const btet *t, const double f[4], btet out[3])
 {
     double fv[4];
     int in[4], ot[4], nin = 0, nout = 0;
+    OPS(4 * 4 * 2);
     for (int v = 0; v < 4; ++v) {
         fv[v] = 0.0;
         for (int i = 0; i < 4; ++i) fv[v] += t->b[v][i] * f[i];
@@ -384,6 +407,7 @@ static void add_piece(const btet *S, const double Dc[4], const double Wc[4], dou
 {
     double v = btet_volume(S);
     if (v == 0.0) return;
+    OPS(4 * 4 * 4 + (unsigned long long)nw * (4 * (2 + OP_CADD) * (form == 1 ? 2 : 1) + 5));
     double D[4], Wv[4], Dm[4];
     for (int q = 0; q < 4; ++q) {
         D[q] = 0.0; Wv[q] = 0.0;
@@ -441,12 +465,15 @@ static void tet_contribution_at(const problem *P, const long long idx[4], const 
                 for (int s = 0; s < n1; ++s) add_piece(&S[s], Dc, Wv, +1.0, 1, nw, omega, P->eta, pacc);
                 continue;
             }
-            int ns = carve_region(a, b, 1, S);
+            OPS(4 * 3);
+            int ns = carve_region(a, b, 1, S), active = ns > 0;
             for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, +1.0, P->form, nw, omega, P->eta, pacc);
             if (P->form == 0) {
                 ns = carve_region(a, b, 2, S);
+                active = active || ns > 0;
                 for (int s = 0; s < ns; ++s) add_piece(&S[s], Dc, Wc, -1.0, 0, nw, omega, P->eta, pacc);
             }
+            t_units += (unsigned long long)active;
         }
 }
 
@@ -510,6 +537,8 @@ static int oracle_mesh(int n1, int n2, int n3, int nb, int no,
     nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
     cplx *acc = (cplx *)calloc((size_t)nt * nw, sizeof(cplx));
+    g_ops = 0;
+    g_units = 0;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(nt)
 #endif
@@ -519,11 +548,20 @@ static int oracle_mesh(int n1, int n2, int n3, int nb, int no,
         tid = omp_get_thread_num();
 #endif
         cplx *my = acc + (size_t)tid * nw;
+        t_ops = 0;
+        t_units = 0;
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
         for (long long cell = cell_begin; cell < cell_end; ++cell)
             for (int t = 0; t < 6; ++t) tet_contribution(&P, cell, t, nw, omega, my, 0);
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+        {
+            g_ops += t_ops;
+            g_units += t_units;
+        }
     }
     double pref = spin_factor / (6.0 * (double)P.nk);
     for (int iw = 0; iw < nw; ++iw) {
@@ -815,4 +853,12 @@ int chi0_oracle_W(int n1, int n2, int n3, int nb, int no,
     memcpy(W, P.W, sizeof(double) * (size_t)P.nbw * P.nbw * P.nk);
     free(P.W);
     return 0;
+}
+
+/* The operation and active-unit counts of the last mesh evaluation (chi0_oracle or
+ * chi0_oracle_z). */
+void chi0_oracle_last_count(unsigned long long *ops, unsigned long long *units)
+{
+    *ops = g_ops;
+    *units = g_units;
 }
