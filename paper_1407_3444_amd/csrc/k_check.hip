@@ -53,6 +53,52 @@ __global__ __launch_bounds__(kScanThreads) void scan_eigvec_kernel(const double 
     }
 }
 
+// Large bases (plane waves, thousands of coefficients per eigenvector): one workgroup per k, so
+// the serial loop over orbitals of the kernel above does not leave HBM idle.  Thread j takes band
+// n = j % nb and the orbitals o = og, og + G, ... with og = j / nb (G = kScanThreads / nb groups);
+// consecutive threads read consecutive coefficients of the k's [no][nb] block.  The G partial sums
+// of each band are added in LDS in a fixed order.
+__global__ __launch_bounds__(kScanThreads) void scan_eigvec_wide_kernel(const double *__restrict__ c, int64_t nk,
+                                                                       int no, int nb, unsigned bit_nonfinite,
+                                                                       unsigned bit_norm, double tol, unsigned *flag)
+{
+    __shared__ double part[kScanThreads];
+    const int j = threadIdx.x;
+    const int G = kScanThreads / nb;
+    const int og = j / nb, n = j - og * nb;
+    unsigned bits = 0u;
+    for (int64_t k = blockIdx.x; k < nk; k += gridDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        if (og < G) {
+            const double *base = c + 2 * (k * no * (int64_t)nb + n);
+            int o = og;
+            for (; o + G < no; o += 2 * G) {
+                const double2 a = *reinterpret_cast<const double2 *>(base + 2 * (int64_t)o * nb);
+                const double2 b = *reinterpret_cast<const double2 *>(base + 2 * (int64_t)(o + G) * nb);
+                s0 = fma(a.x, a.x, fma(a.y, a.y, s0));
+                s1 = fma(b.x, b.x, fma(b.y, b.y, s1));
+            }
+            if (o < no) {
+                const double2 a = *reinterpret_cast<const double2 *>(base + 2 * (int64_t)o * nb);
+                s0 = fma(a.x, a.x, fma(a.y, a.y, s0));
+            }
+        }
+        part[j] = s0 + s1;
+        __syncthreads();
+        if (j < nb) {
+            double s = 0.0;
+            for (int g = 0; g < G; ++g) s += part[g * nb + j];
+            if (!isfinite(s)) bits |= bit_nonfinite;
+            else if (!(fabs(s - 1.0) <= tol)) bits |= bit_norm;
+        }
+        __syncthreads();
+    }
+    const bool any = bits != 0u;
+    if (__ballot(any) != 0ull) {
+        if (any) atomicOr(flag, bits);
+    }
+}
+
 int scan_blocks(int64_t n)
 {
     const int64_t b = (n + kScanThreads - 1) / kScanThreads;
@@ -78,6 +124,12 @@ hipError_t launch_scan_eigvec(const double *c, int64_t nk, int no, int nb, unsig
                               double tol, unsigned *flag, hipStream_t s)
 {
     if (nk <= 0 || no <= 0 || nb <= 0) return hipSuccess;
+    if (no > kMaxOrbSmall && nb <= kScanThreads) {
+        const unsigned nblk = (unsigned)(nk < 65536 ? nk : 65536);
+        hipLaunchKernelGGL(scan_eigvec_wide_kernel, dim3(nblk), dim3(kScanThreads), 0, s, c, nk, no, nb, bit_nonfinite,
+                           bit_norm, tol, flag);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(scan_eigvec_kernel, dim3(scan_blocks(nk * nb)), dim3(kScanThreads), 0, s, c, nk, no, nb,
                        bit_nonfinite, bit_norm, tol, flag);
     return hipGetLastError();

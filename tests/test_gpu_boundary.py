@@ -78,6 +78,36 @@ def test_scan_reports_unnormalised_and_nonfinite_eigenvectors():
     assert e.value.status == -3 and "eigenvector" in str(e.value)
 
 
+def test_scan_of_plane_wave_eigenvectors():
+    """Large bases take the workgroup-per-k scan: 300 plane waves and 6 bands (a band count that
+    does not divide the workgroup, so some threads idle); clean inputs pass, one coefficient of one
+    column scaled (squared norm off by about 1e-3) and one non-finite coefficient are reported."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    wl = synth.plane_wave_workload((4, 4, 3), 300, 6, nq=2, nw=4)
+    dev = torch.device("cuda:0")
+    eps = torch.from_numpy(wl.eps_k).to(dev)
+    plan = lib.Chi0Plan(wl.nk, eps, torch.from_numpy(wl.c_k).to(dev), mu=wl.mu)
+    qs = [lib.Q(shift=q.shift) for q in wl.qs]
+    _say("scan: plane-wave eigenvectors")
+    plan.static(qs)
+    plan.sync()
+    c = wl.c_k.copy()
+    c[17, :, 4] *= np.sqrt(1.001)
+    bad = lib.Chi0Plan(wl.nk, eps, torch.from_numpy(c).to(dev), mu=wl.mu)
+    bad.static(qs)
+    with pytest.raises(lib.Chi0Error) as e:
+        bad.sync()
+    assert e.value.status == -8
+    c = wl.c_k.copy()
+    c[46, 299, 5] = complex(float("nan"), 0.0)
+    bad = lib.Chi0Plan(wl.nk, eps, torch.from_numpy(c).to(dev), mu=wl.mu)
+    bad.static(qs)
+    with pytest.raises(lib.Chi0Error) as e:
+        bad.sync()
+    assert e.value.status == -3 and "eigenvector" in str(e.value)
+
+
 def test_scan_can_be_skipped():
     lib, torch, wl, plan, qs, om, eps, ck = _setup(skip_input_scan=True)
     bad = om.clone()
