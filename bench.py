@@ -138,9 +138,12 @@ def timed_median(fn, reps: int = 3):
     return float(np.median(times)), out
 
 
-# The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch).
-PW_TRAFFIC_KERNEL_SHA = "a205e9b07bc4afcf"
-PW_TRAFFIC_BYTES_PER_LAUNCH = (33201068 * 2.0 + 989042 * 1.0) * 1024
+# The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch), and
+# for the split forms' pair of kernels (the split into packed operands, then the packed-operand
+# contraction; BF16x3 and FP16x3 read and write the same bytes to within 0.1%).
+PW_TRAFFIC_KERNEL_SHA = "37abfa048d66e9db"
+PW_TRAFFIC_BYTES_PER_LAUNCH = (33308888 * 2.0 + 985961 * 1.0) * 1024
+PW_PACKED_TRAFFIC_BYTES_PER_LAUNCH = ((1769505 + 14825630) * 2.0 + (1769814 + 953411) * 1.0) * 1024
 
 
 def kernel_sha(files=("k_tetra.h", "k_tetra_dyn.hip", "chi0_math.h")) -> str:
@@ -301,6 +304,7 @@ def bench_pw(args):
     bytes_launch = (n_pw * nbw * 16.0 * (1 + q_per_launch) + nbw * nbw * 8.0 * q_per_launch) * wl.n_k
     # the roofline counts the flops of the three-product form, the ones the matrix cores must do
     achieved = mfma_flops_launch / (avg_ms * 1e-3) / 1e12
+    pw_sha_ok = kernel_sha(("k_contract.hip",)) == PW_TRAFFIC_KERNEL_SHA
     result = {"metric": METRIC, "value_form": VALUE_FORM, "value": units / (ms * 1e-3),
               "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -312,9 +316,7 @@ def bench_pw(args):
                          "units_per_step": units, "parallelism": "single GPU"},
               "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                           "traffic": (PW_TRAFFIC_BYTES_PER_LAUNCH
-                                       if len(qs) == 16 and kernel_sha(("k_contract.hip",)) == PW_TRAFFIC_KERNEL_SHA
-                                       else None),
+                           "traffic": PW_TRAFFIC_BYTES_PER_LAUNCH if len(qs) == 16 and pw_sha_ok else None,
                            "kernel": "contract_pw_kernel", "avg_launch_ms": round(avg_ms, 3),
                            "algorithmic_bytes_per_launch": bytes_launch,
                            "hbm_bound_ms": round(bytes_launch / 8e12 * 1e3, 3),
@@ -396,6 +398,8 @@ def bench_pw(args):
                        "max_rel_err_of_W_vs_fp64": w_err, "max_rel_err_of_chi0_vs_fp64": chi_err,
                        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
                                     "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+                                    "traffic": (PW_PACKED_TRAFFIC_BYTES_PER_LAUNCH
+                                                if len(qs) == 16 and pw_sha_ok else None),
                                     "kernel": "pack_split_kernel + contract_pw_packed_kernel",
                                     "algorithmic_bytes_per_launch": packed_bytes,
                                     "mfma_tflops": round(split_flops / (m_avg * 1e-3) / 1e12, 1)}}
