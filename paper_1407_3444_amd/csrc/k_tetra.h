@@ -374,12 +374,14 @@ __device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kW
     const int top = qn;
     int nredo = 0;
     auto slot = [&](int p) -> uint16_t & { return queue[F32 ? kQCap - 1 - p : p][lane]; };
+    // the item's result goes to the accumulator of its slot s (a lane-dependent index, so every
+    // slot takes an FMA with a factor 1 or 0: exactly acc + z or acc for a finite result)
     auto add = [&](int s, cplx z) {
 #pragma unroll
         for (int ss = 0; ss < NSLOT; ++ss) {
-            const bool hit = s == ss;
-            acc[ss].re += hit ? z.re : 0.0;
-            acc[ss].im += hit ? z.im : 0.0;
+            const double m = s == ss ? 1.0 : 0.0;
+            acc[ss].re = fma(m, z.re, acc[ss].re);
+            acc[ss].im = fma(m, z.im, acc[ss].im);
         }
     };
     while (__any(qn > 0)) {
