@@ -504,7 +504,9 @@ __global__ __launch_bounds__(kPackThreads) void pack_split_kernel(MeshDev M, u32
     }
 }
 
-constexpr int pw_packed_depth(int nt) { return nt == 1 ? 4 : 2; }
+// Steps of packed operands in flight per wave: four (measured 3% faster than two for 2 x 2 tiles,
+// 238 registers).
+constexpr int kPwPackedDepth = 4;
 
 template <int NT, bool FP16>
 __global__ __launch_bounds__(64 * kPwQ) void contract_pw_packed_kernel(MeshDev M, BatchDev B, int nq, int n_qgroups,
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(64 * kPwQ) void contract_pw_packed_kernel(MeshDev M
     for (int tn = 0; tn < NT; ++tn)
 #pragma unroll
         for (int tm = 0; tm < NT; ++tm) acc[tn][tm].re = acc[tn][tm].re_c = acc[tn][tm].im = acc[tn][tm].im_c = flt4{0.f, 0.f, 0.f, 0.f};
-    constexpr int D = pw_packed_depth(NT);
+    constexpr int D = kPwPackedDepth;
     u32x4 ah[D][NT], al[D][NT], bh[D][NT], bl[D][NT];
     const u32x4 zero = {0u, 0u, 0u, 0u};
     // unconditional loads, clamped to the last block and zeroed past it
