@@ -277,8 +277,10 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
 // and |M|^2 is formed from the three accumulators at the end.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs.  The launch is 1-D and block b runs
-// (k, qgroup) with xcd = b % 8: the q-groups of one k sit on consecutive slots of the same XCD,
-// so their k operand is shared in that XCD's L2.
+// (k, qgroup) with xcd = b % 8, and each XCD takes a contiguous range of k: the q-groups of one k
+// sit on consecutive slots of the same XCD, so their k operand is shared in that XCD's L2, and
+// consecutive k of a band pair (adjacent 8-byte entries of W) are written through the same L2,
+// which merges them into whole sectors.
 // ---------------------------------------------------------------------------
 constexpr int kPwQ = 8;      // q (waves) per workgroup
 constexpr int kXcd = 8;
@@ -291,7 +293,8 @@ __device__ __forceinline__ bool pw_item(const MeshDev &M, int nq, int n_qgroups,
     const int64_t b = blockIdx.x;
     const int xcd = (int)(b % kXcd);
     const int64_t slot = b / kXcd;
-    k = (slot / n_qgroups) * kXcd + xcd;
+    const int64_t k_per_xcd = (M.nk + kXcd - 1) / kXcd;
+    k = xcd * k_per_xcd + slot / n_qgroups;
     qi = (int)(slot % n_qgroups) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
     return k < M.nk && qi < nq;
 }
