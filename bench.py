@@ -55,16 +55,18 @@ def _metrics():
 #   near evaluation repeated in full (items whose entries cluster, counted by the census):
 #        359 + three 2-node entry series of 8 terms (95 each) + two 3-node entry series of 12 terms
 #        (205 each) -> 1054
-#   per final tetrahedron: centre and half-span 4, 50 series coefficients with W-derivatives
-#        (23 each) and offsets 4, class and flags 12 -> 1170; carving (edge parameters and
-#        interpolated corners of the written pieces) about 40
+#   per final tetrahedron: centre and half-span 4, offsets 4, class and flags 12 -> 20; carving
+#        (edge parameters and interpolated corners of the written pieces) about 40; plus 23 per
+#        series coefficient with its W-derivative, computed for the blocks of terms the series
+#        class reads (the census counts them; 50 for every tetrahedron in earlier kernels)
 #   the logarithm (own routine): range reduction 3, reciprocal 7, 11-term atanh series 23, scale
 #        and ln2 terms 8 -> 41
 FLOPS_FAR_BASE = 10
 FLOPS_PER_TERM = 2
 FLOPS_NEAR_FIRST = 359
 FLOPS_NEAR_FULL = 1054
-FLOPS_PER_FINAL_TET = 1170 + 40
+FLOPS_PER_FINAL_TET = 20 + 40
+FLOPS_PER_COEF = 23
 # Mixed form: the series in FP32 (20 terms at ratio 0.4), the near branch in FP32 except near-
 # degenerate tetrahedra; the same formulas with the FP32 logarithm (hardware, 3) and 10-term
 # entry series, one pass: 886 per near evaluation; coefficients still FP64 (20 terms: 480).
@@ -91,7 +93,7 @@ def census_flops(census: dict, mixed: bool = False) -> int:
                 + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET_MIXED)
     return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
             + census["near_evals"] * FLOPS_NEAR_FIRST + census.get("near_redo", 0) * FLOPS_NEAR_FULL
-            + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET)
+            + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET + census["coef_terms"] * FLOPS_PER_COEF)
 
 
 def host_cores() -> dict:

@@ -270,7 +270,7 @@ chi0_status chi0_profile_enable(chi0_plan_t plan, int32_t enable);
 chi0_status chi0_profile_read(chi0_plan_t plan, chi0_profile *out);
 
 /* Work census of chi0_dynamic(plan, nq, qs, nw, omega) (diagnostic): the same evaluation with
- * counters, its result discarded.  counts (host uint64 [6]) receives the number of (tetrahedron,
+ * counters, its result discarded.  counts (host uint64 [7]) receives the number of (tetrahedron,
  * band pair, q) units whose carved region is non-empty, the number of final tetrahedra, the
  * number of (final tetrahedron, frequency) evaluations taking the near branch, the number of
  * far-branch series evaluations (one per final tetrahedron and frequency, or one per list of up
@@ -278,8 +278,9 @@ chi0_status chi0_profile_read(chi0_plan_t plan, chi0_profile *out);
  * list's series are summed into one), the series terms summed over those evaluations (each cut
  * to the terms its distance from the frequencies needs), and the near evaluations that the FP64
  * form repeats in full because a divided-difference entry's nodes cluster (its first pass skips
- * every entry's Taylor series).  Uses the same workspace as chi0_dynamic and synchronises the
- * stream. */
+ * every entry's Taylor series), and the far-series coefficients computed for the final
+ * tetrahedra (only the blocks of terms their series class, or their list's, reads).  Uses the
+ * same workspace as chi0_dynamic and synchronises the stream. */
 chi0_status chi0_census(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
                         const double *omega, void *workspace, size_t workspace_bytes,
                         uint64_t *counts);

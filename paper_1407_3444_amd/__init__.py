@@ -454,11 +454,11 @@ class Chi0Plan:
         nw, op = self._omega(omega)
         arr = self._qarray(qs)
         ws, (wp, wn) = self._ws(workspace, nq, nw)
-        counts = (ctypes.c_uint64 * 6)()
+        counts = (ctypes.c_uint64 * 7)()
         self._check(self._lib.chi0_census(self._h, nq, arr, nw, op, wp, wn, counts), "chi0_census")
         return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
                 "near_evals": int(counts[2]), "far_evals": int(counts[3]), "far_terms": int(counts[4]),
-                "near_redo": int(counts[5])}
+                "near_redo": int(counts[5]), "coef_terms": int(counts[6])}
 
 
 def iw_cubic(n: int):

@@ -231,7 +231,7 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0, bool packed
                        ? align_up(pack_bytes(p->mesh))
                        : 0;
     L.count_off = L.pack_off + L.pack_bytes;
-    L.flag_off = L.count_off + 128;       // census counters (48 bytes), then the scan verdict
+    L.flag_off = L.count_off + 128;       // census counters (56 bytes), then the scan verdict
     L.total = L.count_off + kAlign;
     return L;
 }
@@ -610,7 +610,7 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
     auto *dc = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + L.count_off);
     double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
     if ((st = enqueue_scan(p, nq, qs, omega, nw, scan_flag(ws, L))) != CHI0_OK) return st;
-    hipError_t e = hipMemsetAsync(dc, 0, 6 * sizeof(unsigned long long), p->stream);
+    hipError_t e = hipMemsetAsync(dc, 0, 7 * sizeof(unsigned long long), p->stream);
     if (e != hipSuccess) return device_fail(p, e, "census clear");
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
@@ -624,11 +624,11 @@ chi0_status chi0_census(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw,
                 return device_fail(p, e, "census kernel");
         }
     }
-    unsigned long long h[6];
+    unsigned long long h[7];
     if ((e = hipMemcpyAsync(h, dc, sizeof h, hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(p->stream)) != hipSuccess)
         return device_fail(p, e, "census copy");
-    for (int i = 0; i < 6; ++i) counts[i] = h[i];
+    for (int i = 0; i < 7; ++i) counts[i] = h[i];
     return CHI0_OK;
 }
 

@@ -243,6 +243,37 @@ C0_HD void far_coeffs(const double y[4], const double w[4], double c, double *a)
     }
 }
 
+// The same coefficients in blocks of K / NB terms, only the first nblocks blocks (the terms a
+// class-cut Horner sum reads); a[] past them is left untouched.
+template <int K, int NB>
+C0_HD void far_coeffs_blocks(const double y[4], const double w[4], double c, double *a, int nblocks)
+{
+    constexpr int S = K / NB;
+    double z0 = y[0] - c, z1 = y[1] - c, z2 = y[2] - c, z3 = y[3] - c;
+    double P0 = 1.0, P1 = 1.0, P2 = 1.0, P3 = 1.0;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nblocks) continue;        // (not break: the loop stays unrolled)
+#pragma unroll
+        for (int j = 1; j <= S; ++j) {
+            const int m = b * S + j;
+            double n0 = z0 * P0;
+            double e0 = fma(w[0], P0, z0 * d0);
+            double n1 = fma(z1, P1, n0);
+            double e1 = fma(w[1], P1, fma(z1, d1, e0));
+            double n2 = fma(z2, P2, n1);
+            double e2 = fma(w[2], P2, fma(z2, d2, e1));
+            double n3 = fma(z3, P3, n2);
+            double e3 = fma(w[3], P3, fma(z3, d3, e2));
+            P0 = n0; P1 = n1; P2 = n2; P3 = n3;
+            d0 = e0; d1 = e1; d2 = e2; d3 = e3;
+            const double mm = (double)m;
+            a[m - 1] = 6.0 / (mm * (mm + 1.0) * (mm + 2.0) * (mm + 3.0)) * e3;
+        }
+    }
+}
+
 template <int K = kFarTerms>
 C0_HD double far_horner(const double *a, double t)
 {

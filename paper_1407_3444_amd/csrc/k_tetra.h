@@ -424,7 +424,7 @@ __device__ __forceinline__ void drain_near(const Rec *list, uint16_t (*queue)[kW
 
 // Work counted by the census instantiation (COUNT) of the dynamic body, wave totals.
 struct WorkCount {
-    unsigned long long units, tets, near, far, terms, redo;
+    unsigned long long units, tets, near, far, terms, redo, coef;
 };
 
 // One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
@@ -503,22 +503,36 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
             const double C = 0.5 * (clo + chi), R = 0.5 * (chi - clo);
             const double distC = fmax(fmax(wlo - C, C - whi), 0.0);
             const bool cluster = R < kRho * distC;
+            const int clsC = far_class(R, distC, fmax(fabs(wlo - C), fabs(whi - C)), kRho);
+            if (COUNT && count_tets) {
+                // coefficients computed below (blocks of kFarTerms / kFarClasses terms)
+                int nb = 0;
+                if (mine) {
+                    const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
+                    nb = MIXED ? kFarClasses
+                               : (cluster ? clsC : far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho));
+                }
+                wc->coef += (unsigned long long)wave_sum(nb) * ((MIXED ? kFarTerms32 : kFarTerms) / kFarClasses);
+            }
             if (mine) {
                 const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
                 const double cc = cluster ? C : c0;
+                const int cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
                 if constexpr (MIXED) {
                     double a[kFarTerms32];
                     far_coeffs<kFarTerms32>(y, w, cc, a);
 #pragma unroll
                     for (int m = 0; m < kFarTerms32; ++m) list[lane].a32[m] = (float)a[m];
                 } else {
-                    far_coeffs(y, w, cc, list[lane].a);
+                    // only the blocks of terms a Horner sum reads: the tetrahedron's own class, or
+                    // the list's when the list is summed as one series (later ones stay unread)
+                    far_coeffs_blocks<kFarTerms, kFarClasses>(y, w, cc, list[lane].a, cluster ? clsC : cls);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { list[lane].y[k] = y[k]; list[lane].w[k] = w[k]; }
                 list[lane].c = c0;
                 list[lane].hs = hs0;
-                list[lane].cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
+                list[lane].cls = cls;
                 list[lane].flags = (hs0 < kRho * dist ? 1 : 0) | (near_degenerate(y, M.degen_tol, M.degen_rel) ? 2 : 0);
             }
             __syncthreads();
@@ -526,7 +540,6 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 // coefficients of the list about C, summed over the tetrahedra in list order into
                 // the (empty) near queue's memory, then one Horner evaluation per frequency
                 double *acl = reinterpret_cast<double *>(&queue[0][0]);
-                const int clsC = far_class(R, distC, fmax(fabs(wlo - C), fabs(whi - C)), kRho);
                 constexpr int KC = MIXED ? kFarTerms32 : kFarTerms;
                 if (lane < KC) {
                     double sum = 0.0;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
     __shared__ DynRec<MIXED> list[kCapDyn];
     __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
     const int qi = blockIdx.y;
-    WorkCount wc = {0, 0, 0, 0, 0, 0};
+    WorkCount wc = {0, 0, 0, 0, 0, 0, 0};
     dynamic_body<8, MIXED, LIST, true>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
                                        partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue, &wc,
                                        count_tets != 0);
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
         atomicAdd(&counts[3], wc.far);
         atomicAdd(&counts[4], wc.terms);
         atomicAdd(&counts[5], wc.redo);
+        atomicAdd(&counts[6], wc.coef);
     }
 }
 

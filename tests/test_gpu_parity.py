@@ -482,6 +482,8 @@ def test_census_counts_the_evaluation():
     assert 0 < got["near_evals"] and 0 < got["far_evals"]
     assert got["near_evals"] + got["far_evals"] <= host_tets * nw
     assert got["far_terms"] >= got["far_evals"]
+    # series coefficients: whole blocks of 5 terms, at most the 50 of the series per tetrahedron
+    assert got["coef_terms"] % 5 == 0 and 0 < got["coef_terms"] <= 50 * host_tets
 
 
 def test_nonfinite_frequency_only_affects_itself():
