@@ -69,9 +69,11 @@ FLOPS_PER_FINAL_TET = 20 + 40
 FLOPS_PER_COEF = 23
 # Mixed form: the series in FP32 (20 terms at ratio 0.4), the near branch in FP32 except near-
 # degenerate tetrahedra; the same formulas with the FP32 logarithm (hardware, 3) and 10-term
-# entry series, one pass: 886 per near evaluation; coefficients still FP64 (20 terms: 480).
+# entry series, one pass: 886 per near evaluation; coefficients still computed in FP64 and
+# rounded to FP32 (24 each, the blocks the class reads, counted by the census).
 FLOPS_NEAR_FULL_FP32 = 886
-FLOPS_PER_FINAL_TET_MIXED = 480 + 16 + 40
+FLOPS_PER_FINAL_TET_MIXED = 16 + 40
+FLOPS_PER_COEF_MIXED = 24
 FP64_PEAK_TFLOPS = 78.6      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk (vector)
 FP32_PEAK_TFLOPS = 157.3     # published FP32 vector peak (packed FP32; this library is built without it)
 HBM_PEAK_GBS = 8000.0        # published HBM3E bandwidth
@@ -90,7 +92,7 @@ def census_flops(census: dict, mixed: bool = False) -> int:
     if mixed:
         return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
                 + census["near_evals"] * FLOPS_NEAR_FULL_FP32
-                + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET_MIXED)
+                + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET_MIXED + census["coef_terms"] * FLOPS_PER_COEF_MIXED)
     return (census["far_evals"] * FLOPS_FAR_BASE + census["far_terms"] * FLOPS_PER_TERM
             + census["near_evals"] * FLOPS_NEAR_FIRST + census.get("near_redo", 0) * FLOPS_NEAR_FULL
             + census["final_tetrahedra"] * FLOPS_PER_FINAL_TET + census["coef_terms"] * FLOPS_PER_COEF)

@@ -509,8 +509,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 int nb = 0;
                 if (mine) {
                     const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
-                    nb = MIXED ? kFarClasses
-                               : (cluster ? clsC : far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho));
+                    nb = cluster ? clsC : far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
                 }
                 wc->coef += (unsigned long long)wave_sum(nb) * ((MIXED ? kFarTerms32 : kFarTerms) / kFarClasses);
             }
@@ -518,14 +517,14 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
                 const double dist = fmax(fmax(wlo - c0, c0 - whi), 0.0);
                 const double cc = cluster ? C : c0;
                 const int cls = far_class(hs0, dist, fmax(fabs(wlo - c0), fabs(whi - c0)), kRho);
+                // only the blocks of terms a Horner sum reads: the tetrahedron's own class, or the
+                // list's when the list is summed as one series (later ones stay unread)
                 if constexpr (MIXED) {
-                    double a[kFarTerms32];
-                    far_coeffs<kFarTerms32>(y, w, cc, a);
+                    double a[kFarTerms32] = {};
+                    far_coeffs_blocks<kFarTerms32, kFarClasses>(y, w, cc, a, cluster ? clsC : cls);
 #pragma unroll
                     for (int m = 0; m < kFarTerms32; ++m) list[lane].a32[m] = (float)a[m];
                 } else {
-                    // only the blocks of terms a Horner sum reads: the tetrahedron's own class, or
-                    // the list's when the list is summed as one series (later ones stay unread)
                     far_coeffs_blocks<kFarTerms, kFarClasses>(y, w, cc, list[lane].a, cluster ? clsC : cls);
                 }
 #pragma unroll
