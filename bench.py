@@ -680,7 +680,8 @@ def main():
     ap.add_argument("--kk", type=int, default=0, metavar="N_SPEC",
                     help="dynamic workloads: also time the Kramers-Kronig route with N_SPEC spectral points")
     ap.add_argument("--pairs", action="store_true",
-                    help="static workloads: time the band-pair resolved call (chi0_static_pairs)")
+                    help="time the band-pair resolved call (chi0_static_pairs, or chi0_dynamic_pairs for "
+                         "dynamic workloads)")
     ap.add_argument("--n-keep", type=int, default=9, help="band window of bcc_dynamic")
     ap.add_argument("--sweep", action="store_true",
                     help="bcc_dynamic with all 9 bands: also time the 7- and 5-band windows and report "
@@ -857,6 +858,26 @@ def main():
                                             "frac above uses the census count"}
         log(f"oracle op count: {per_unit_w:.0f} flops per active unit and w; "
             f"{o_rate:.0f} TFLOP/s oracle-equivalent ({o_rate / FP64_PEAK_TFLOPS:.1f}x the FP64 peak)")
+
+    if args.pairs:
+        # the same step resolved by band pair (one output per q, pair and frequency)
+        pws = torch.empty(plan.dynamic_pairs_workspace_bytes(len(qs), nw), dtype=torch.uint8, device=dev)
+        pout = torch.empty((len(qs), nbw, nbw, nw, 2), dtype=torch.float64, device=dev)
+        plan.dynamic_pairs(qs, om, workspace=pws, out=pout)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for i in range(args.steps):
+            plan.dynamic_pairs(qs, om, workspace=pws, out=pout)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1) / args.steps
+        psum = pout.sum(dim=(1, 2))
+        pdiff = float((psum - out).abs().max() / out.abs().max())
+        result["pairs"] = {"ms_per_step": pms, "time_vs_dynamic": pms / ms_step,
+                           "workspace_bytes": pws.numel(), "max_rel_diff_of_pair_sum_vs_dynamic": pdiff}
+        log(f"pair-resolved dynamic: {pms:.1f} ms/step ({pms / ms_step:.2f}x), pair sum vs dynamic {pdiff:.1e}")
+        del pws, pout
 
     if not args.no_mixed:
         # mixed forms: split BF16 / FP16 MFMA matrix elements, FP32 weights with the FP64 near branch

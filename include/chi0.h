@@ -163,6 +163,19 @@ chi0_status chi0_dynamic(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t
                          const double *omega, void *workspace, size_t workspace_bytes,
                          double *chi);
 
+/* Dynamic chi0(q, w) resolved by band pair (the per-pair analysis of Sec. III at every
+ * frequency): chi: device float64 [nq][nbw][nbw][nw][2]; entry (q, n, m, w) holds the terms of
+ * band n at k and band m at k+q, so the sum over (n, m) is chi0_dynamic's result (to the rounding
+ * of the different summation order).  Each band pair's units are evaluated by workgroups of their
+ * own.  Mesh plans only (a tetrahedron-list plan returns CHI0_E_UNSUPPORTED).  The workspace is
+ * given by chi0_dynamic_pairs_workspace_size: the matrix elements of one q batch and
+ * nbw^2 x (up to 16) partial sums per q and frequency. */
+chi0_status chi0_dynamic_pairs(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
+                               const double *omega, void *workspace, size_t workspace_bytes, double *chi);
+
+/* Device workspace (bytes) of chi0_dynamic_pairs for nq q-points and nw frequencies. */
+chi0_status chi0_dynamic_pairs_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, size_t *bytes);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): chi0_dynamic with its workspace in a fixed device array
  * of the library, 128 MiB per device (held from the first call on a device until the process

@@ -22,7 +22,7 @@ __all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library"
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 
 EXPORTED_SYMBOLS = ["chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
-                    "chi0_dynamic_noalloc",
+                    "chi0_dynamic_noalloc", "chi0_dynamic_pairs", "chi0_dynamic_pairs_workspace_size",
                     "chi0_kk_workspace_size", "chi0_dynamic_kk", "chi0_plan_list", "chi0_static_group",
                     "chi0_dynamic_group", "chi0_iw_cubic",
                     "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH):
                                     vp, sz, vp]
     lib.chi0_dynamic.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
     lib.chi0_dynamic_noalloc.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp]
+    lib.chi0_dynamic_pairs.argtypes = [vp, i32, ctypes.POINTER(_Q), i32, vp, vp, sz, vp]
+    lib.chi0_dynamic_pairs_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     lib.chi0_matrix_elements.argtypes = [vp, ctypes.POINTER(_Q), vp]
     lib.chi0_profile_enable.argtypes = [vp, i32]
     lib.chi0_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
@@ -127,7 +129,7 @@ def load_library(path: str = LIB_PATH):
     lib.chi0_batch_last_error.argtypes = [vp]
     lib.chi0_batch_last_error.restype = ctypes.c_char_p
     for name in ("chi0_plan", "chi0_workspace_size", "chi0_static", "chi0_static_pairs", "chi0_dynamic",
-                 "chi0_dynamic_noalloc",
+                 "chi0_dynamic_noalloc", "chi0_dynamic_pairs", "chi0_dynamic_pairs_workspace_size",
                  "chi0_kk_workspace_size", "chi0_dynamic_kk",
                  "chi0_matrix_elements", "chi0_profile_enable", "chi0_profile_read", "chi0_census",
                  "chi0_sync", "chi0_destroy", "chi0_batch_workspace_size", "chi0_batch_create", "chi0_batch_run",
@@ -367,6 +369,29 @@ class Chi0Plan:
         chi = _out_f64(out if out is not None else self._new((nq, nw, 2)), (nq, nw, 2), "out")
         self._check(self._lib.chi0_dynamic(self._h, nq, arr, nw, op, wp, wn, ctypes.c_void_p(chi.data_ptr())),
                     "chi0_dynamic")
+        return torch.view_as_complex(chi)
+
+    def dynamic_pairs_workspace_bytes(self, nq: int, nw: int) -> int:
+        n = ctypes.c_size_t()
+        self._check(self._lib.chi0_dynamic_pairs_workspace_size(self._h, nq, nw, ctypes.byref(n)),
+                    "chi0_dynamic_pairs_workspace_size")
+        return int(n.value)
+
+    def dynamic_pairs(self, qs: Sequence[Q], omega, workspace=None, out=None):
+        """chi0(q, w) resolved by band pair: complex128 tensor [nq, nbw, nbw, nw] (n at k, m at k+q;
+        out: float64 [nq, nbw, nbw, nw, 2] or complex128 [nq, nbw, nbw, nw]).  Mesh plans only."""
+        import torch
+        nq = len(qs)
+        nw, op = self._omega(omega)
+        arr = self._qarray(qs)
+        if workspace is None:
+            workspace = torch.empty(self.dynamic_pairs_workspace_bytes(nq, nw), dtype=torch.uint8,
+                                    device=self.eps_k.device)
+        wp, wn = _workspace_ptr(workspace)
+        shape = (nq, self.nbw, self.nbw, nw, 2)
+        chi = _out_f64(out if out is not None else self._new(shape), shape, "out")
+        self._check(self._lib.chi0_dynamic_pairs(self._h, nq, arr, nw, op, wp, wn, ctypes.c_void_p(chi.data_ptr())),
+                    "chi0_dynamic_pairs")
         return torch.view_as_complex(chi)
 
     def dynamic_noalloc(self, qs: Sequence[Q], omega, out):

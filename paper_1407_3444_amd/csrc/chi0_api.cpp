@@ -271,6 +271,30 @@ KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
     return L;
 }
 
+// Workspace of the pair-resolved dynamic call: W of one q batch, then the partial sums
+// [q][pair][nblk][2 nwc] (nblk workgroups per pair, up to 16, each at least 4 rounds), then the
+// scan verdict.
+struct PairsLayout {
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, flag_off, total;
+    int qbatch, nblk;
+};
+
+PairsLayout dpairs_layout(const chi0_plan_s *p, int nq, int nvals)
+{
+    PairsLayout L;
+    L.qbatch = std::min(nq, p->qbatch);
+    const int64_t rounds = (tets_per_pair(p->mesh) + kWave - 1) / kWave;
+    L.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (rounds + 3) / 4));
+    L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
+    L.part_bytes_per_q =
+        align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * (size_t)L.nblk * (size_t)nvals);
+    L.w_off = 0;
+    L.part_off = L.w_bytes_per_q * L.qbatch;
+    L.flag_off = L.part_off + L.part_bytes_per_q * L.qbatch;
+    L.total = L.flag_off + kAlign;
+    return L;
+}
+
 chi0_status check_qs(chi0_plan_t p, int32_t nq, const chi0_q *qs)
 {
     if (nq < 1 || !qs) return fail(p, CHI0_E_INVALID_ARG, "nq must be >= 1 and qs non-null");
@@ -790,6 +814,63 @@ chi0_status chi0_dynamic(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw
     if (!p) return CHI0_E_INVALID_ARG;
     // the workspace chi0_workspace_size reports is exactly the layout of the plan's own batch
     return dynamic_run(p, nq, qs, nw, omega, ws, ws_bytes, chi, 0, false);
+}
+
+chi0_status chi0_dynamic_pairs_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, size_t *bytes)
+{
+    if (!p || !bytes) return CHI0_E_INVALID_ARG;
+    if (nq < 1 || nw < 1) return fail(p, CHI0_E_INVALID_ARG, "nq and nw must be >= 1");
+    *bytes = dpairs_layout(p, nq, 2 * std::min(nw, kMaxOmegaPerLaunch)).total;
+    return CHI0_OK;
+}
+
+chi0_status chi0_dynamic_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t nw, const double *omega,
+                               void *ws, size_t ws_bytes, double *chi)
+{
+    if (!p) return CHI0_E_INVALID_ARG;
+    chi0_status st = begin_call(p);
+    if (st) return st;
+    if (p->list) return fail(p, CHI0_E_UNSUPPORTED, "the pair-resolved dynamic call takes mesh plans");
+    st = check_qs(p, nq, qs);
+    if (st) return st;
+    if (nw < 1 || !omega || !chi) return fail(p, CHI0_E_INVALID_ARG, "nw >= 1, omega and chi non-null required");
+    const int nwc_max = std::min(nw, kMaxOmegaPerLaunch);
+    const PairsLayout L = dpairs_layout(p, nq, 2 * nwc_max);
+    if (!ws || ws_bytes < L.total) return fail(p, CHI0_E_WORKSPACE, "workspace too small");
+    unsigned *flag = reinterpret_cast<unsigned *>(static_cast<char *>(ws) + L.flag_off);
+    if ((st = enqueue_scan(p, nq, qs, omega, nw, flag)) != CHI0_OK) return st;
+    const int npairs = p->mesh.nbw * p->mesh.nbw;
+    double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) + L.part_off);
+    const double scale = prefactor(p);
+    Layout Lw = {};   // W of the batch at the start of the workspace, as for chi0_dynamic
+    Lw.w_off = L.w_off;
+    Lw.w_bytes_per_q = L.w_bytes_per_q;
+    PackState pk = {nullptr, false};
+    for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
+        const int nqb = std::min(L.qbatch, nq - q0);
+        BatchDev B;
+        fill_batch(p, qs, q0, nqb, ws, Lw, B);
+        hipError_t e;
+        if (!p->d.cma && (e = timed(p, 0, [&] {
+                              return launch_contract(p->mesh, B, nqb, p->d.precision, &pk, p->stream);
+                          })) != hipSuccess)
+            return device_fail(p, e, "matrix-element kernel");
+        for (int w0 = 0; w0 < nw; w0 += kMaxOmegaPerLaunch) {
+            const int nwc = std::min(kMaxOmegaPerLaunch, nw - w0);
+            if ((e = timed(p, 1, [&] {
+                     return launch_tetra_dynamic_pairs(p->mesh, B, nqb, L.nblk, omega + w0, nwc, partial,
+                                                       p->d.precision != 0, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "tetrahedron kernel");
+            // groups (q, pair) in order: out[((q0 + q) npairs + pair) nw + w][2]
+            if ((e = timed(p, 2, [&] {
+                     return launch_reduce(partial, nqb * npairs, L.nblk, 2 * nwc, scale,
+                                          chi + ((int64_t)q0 * npairs * nw + w0) * 2, (int64_t)nw * 2, p->stream);
+                 })) != hipSuccess)
+                return device_fail(p, e, "reduce kernel");
+        }
+    }
+    return CHI0_OK;
 }
 
 chi0_status chi0_kk_workspace_size(chi0_plan_t p, int32_t nq, int32_t nw, int32_t n_spec, size_t *bytes)

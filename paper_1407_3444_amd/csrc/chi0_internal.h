@@ -116,6 +116,9 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
                                 const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 hipError_t launch_tetra_dynamic_list(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks,
                                      const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
+// K_B dynamic resolved by band pair (mesh plans): partial[nq][nbw*nbw][nblk][nw][2].
+hipError_t launch_tetra_dynamic_pairs(const MeshDev &mesh, const BatchDev &batch, int nq, int nblk,
+                                      const double *omega, int nw, double *partial, bool mixed, hipStream_t s);
 
 // Census of the work of a dynamic call (nw <= kMaxOmegaPerLaunch), by the dynamic evaluation
 // itself with counters (it also writes the call's partial sums): counts[0..5] += active units,

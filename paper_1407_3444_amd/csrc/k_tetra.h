@@ -428,17 +428,18 @@ struct WorkCount {
 };
 
 // One workgroup of the dynamic evaluation of one q: workgroup blk of nblocks, writing its
-// partial sums for every frequency to part[nw][2].  With COUNT the same evaluation also counts
+// partial sums for every frequency to part[nw][2].  The units are [u0, u1) (u1 < 0: all of them;
+// a band pair's units are consecutive, for the pair-resolved call).  With COUNT the same evaluation also counts
 // its work into *wc (units with a non-empty carved region and final tetrahedra only when
 // count_tets is set, so that a frequency grid split over launches counts them once).
 template <int NSLOT, bool MIXED, bool LIST, bool COUNT = false>
 __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, int nblocks, int blk,
                                              const double *__restrict__ omega, int nw, double *__restrict__ part,
                                              DynRec<MIXED> *list, uint16_t (*queue)[kWave], WorkCount *wc = nullptr,
-                                             bool count_tets = false)
+                                             bool count_tets = false, int64_t u0 = 0, int64_t u1 = -1)
 {
     const int lane = threadIdx.x;
-    const int64_t n_units = tets_per_pair(M) * M.nbw * M.nbw;
+    const int64_t n_units = u1 < 0 ? tets_per_pair(M) * M.nbw * M.nbw : u1;
     constexpr double kRho = MIXED ? kRhoFar32 : kRhoFar;     // far ratio of the series in use
 
     // frequencies of this lane (slot s holds w[lane + 64 s]; dead lanes repeat the last one)
@@ -463,7 +464,7 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
 
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
     // samples all band pairs, so the work per workgroup is even
-    for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
+    for (int64_t base = u0 + (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
         const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
         const bool valid = base + lane < n_units;
         int cnt = 0;
@@ -691,6 +692,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void te
     const int qi = blockIdx.y;
     dynamic_body<NSLOT, MIXED, LIST>(M, B.q[qi], nblocks, blockIdx.x, omega, nw,
                                partial + ((int64_t)qi * nblocks + blockIdx.x) * nw * 2, list, queue);
+}
+
+// Band-pair resolved dynamic evaluation (mesh plans): workgroup x = p * nblk + j takes the units of
+// pair p as part j of nblk; partial[q][pair][j][nw][2].
+template <int NSLOT, bool MIXED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tetra_dynamic_pairs_kernel(
+    MeshDev M, BatchDev B, int nblk, const double *__restrict__ omega, int nw, double *__restrict__ partial)
+{
+    __shared__ DynRec<MIXED> list[kCapDyn];
+    __shared__ __attribute__((aligned(16))) uint16_t queue[kQCap][kWave];
+    const int qi = blockIdx.y;
+    const int npairs = M.nbw * M.nbw;
+    const int p = blockIdx.x / nblk, j = blockIdx.x - p * nblk;
+    const int64_t per_pair = tets_per_pair(M);
+    dynamic_body<NSLOT, MIXED, false>(M, B.q[qi], nblk, j, omega, nw,
+                                      partial + (((int64_t)qi * npairs + p) * nblk + j) * nw * 2, list, queue, nullptr,
+                                      false, (int64_t)p * per_pair, (int64_t)(p + 1) * per_pair);
 }
 
 // Static evaluation (w = 0, Re only) of units [u0, u1) by workgroup blk of nblocks: rounds of

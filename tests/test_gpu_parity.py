@@ -486,6 +486,44 @@ def test_census_counts_the_evaluation():
     assert got["coef_terms"] % 5 == 0 and 0 < got["coef_terms"] <= 50 * host_tets
 
 
+@pytest.mark.parametrize("precision,nw", [(0, 40), (0, 600), (1, 40)])
+def test_dynamic_pairs_match_oracle_and_the_pair_sum(precision, nw):
+    """chi0_dynamic_pairs: chi0(q, w) of every band pair (n at k, m at k+q) against the oracle's
+    pair-resolved evaluation, per result against max(|ref|, 1e-3 of the largest |ref| of any pair);
+    the sum over pairs equals chi0_dynamic's result to rounding in FP64 (another summation order)
+    and within the mixed-form bar in the mixed form (whose FP32 series are cut and summed per list,
+    and the lists differ when each pair has lists of its own); 600 frequencies take two launches."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    wl = synth.make_workload("tetra_dynamic", nk=(6, 6, 2), nq=8, q_subset=[3], nw=nw)
+    wl.band_lo, wl.band_hi = 2, 8
+    plan, qs = _plan(wl, precision=precision)
+    om = torch.from_numpy(wl.omega).cuda()
+    _say("dynamic pairs, precision", precision, "nw", nw)
+    got = plan.dynamic_pairs(qs, om).cpu().numpy()[0]            # [nbw][nbw][nw]
+    ref = oracle.chi0_pairs(wl, 0)
+    scale = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+    err = np.max(np.abs(got - ref) / scale)
+    _say(f"per-pair per-result error {err:.2e}")
+    assert err <= (TOL if precision == 0 else 1e-5)
+    total = plan.dynamic(qs, om).cpu().numpy()[0]
+    bound = 1e-13 if precision == 0 else 1e-5
+    assert np.max(np.abs(got.sum(axis=(0, 1)) - total)) <= bound * np.max(np.abs(total))
+
+
+def test_dynamic_pairs_rejects_list_plans():
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    dev = torch.device("cuda:0")
+    eps = torch.zeros((1, 4), dtype=torch.float64, device=dev)
+    tets = torch.tensor([[0, 1, 2, 3]], dtype=torch.int32, device=dev)
+    plan = lib.Chi0Plan(None, eps, None, cma=True, tetrahedra=(tets, 1.0))
+    q = lib.Q(eps_kq=eps.clone())
+    with pytest.raises(lib.Chi0Error) as e:
+        plan.dynamic_pairs([q], torch.zeros(4, dtype=torch.float64, device=dev))
+    assert e.value.status == -7
+
+
 def test_nonfinite_frequency_only_affects_itself():
     """A NaN or infinite frequency does not stop the call: a NaN gives NaN at its own frequency and
     leaves every other one bit for bit unchanged; an infinite frequency (whose own value is not
