@@ -168,8 +168,8 @@ chi0_status chi0_dynamic(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t
  * band n at k and band m at k+q, so the sum over (n, m) is chi0_dynamic's result (to the rounding
  * of the different summation order).  Each band pair's units are evaluated by workgroups of their
  * own.  Mesh plans only (a tetrahedron-list plan returns CHI0_E_UNSUPPORTED).  The workspace is
- * given by chi0_dynamic_pairs_workspace_size: the matrix elements of one q batch and
- * nbw^2 x (up to 16) partial sums per q and frequency. */
+ * given by chi0_dynamic_pairs_workspace_size: the matrix elements of one q batch and up to
+ * min(64 nbw^2, 8192) partial sums per q and frequency. */
 chi0_status chi0_dynamic_pairs(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
                                const double *omega, void *workspace, size_t workspace_bytes, double *chi);
 

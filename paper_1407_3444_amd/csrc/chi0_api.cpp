@@ -272,8 +272,7 @@ KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
 }
 
 // Workspace of the pair-resolved dynamic call: W of one q batch, then the partial sums
-// [q][pair][nblk][2 nwc] (nblk workgroups per pair, up to 16, each at least 4 rounds), then the
-// scan verdict.
+// [q][pair][nblk][2 nwc] (nblk workgroups per pair), then the scan verdict.
 struct PairsLayout {
     size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, flag_off, total;
     int qbatch, nblk;
@@ -284,7 +283,12 @@ PairsLayout dpairs_layout(const chi0_plan_s *p, int nq, int nvals)
     PairsLayout L;
     L.qbatch = std::min(nq, p->qbatch);
     const int64_t rounds = (tets_per_pair(p->mesh) + kWave - 1) / kWave;
-    L.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(16, (rounds + 3) / 4));
+    // up to 64 workgroups per pair (16 measured 1.7x slower on the 100-pair workload: a pair's work
+    // is uneven and lands on too few workgroups), at most 8192 per q so the partial sums stay
+    // within 64 MiB per q at 512 frequencies, each at least 4 rounds
+    const int64_t npairs = (int64_t)p->mesh.nbw * p->mesh.nbw;
+    const int64_t cap = std::min<int64_t>(64, std::max<int64_t>(4, 8192 / npairs));
+    L.nblk = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (rounds + 3) / 4));
     L.w_bytes_per_q = p->d.cma ? 0 : align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * p->mesh.nk);
     L.part_bytes_per_q =
         align_up(sizeof(double) * (size_t)p->mesh.nbw * p->mesh.nbw * (size_t)L.nblk * (size_t)nvals);
