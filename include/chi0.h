@@ -188,8 +188,9 @@ chi0_status chi0_dynamic_pairs_workspace_size(chi0_plan_t plan, int32_t nq, int3
 chi0_status chi0_dynamic_noalloc(chi0_plan_t plan, int32_t nq, const chi0_q *qs, int32_t nw,
                                  const double *omega, double *chi);
 
-/* The Kramers-Kronig route (Sec. II: one usually computes Im chi0 only and obtains Re chi0 from it
- * by the Kramers-Kronig relation, provided the frequencies cover the whole spectrum).
+/* The Kramers-Kronig route (Sec. II: the common practice is to compute Im chi0 alone and to
+ * recover Re chi0 by a Kramers-Kronig transform, which needs a frequency grid over the whole
+ * spectrum).
  * Im chi0 is computed exactly (tetrahedron delta weights, no logarithms) at the requested
  * frequencies omega (device float64 [nw]) and on the uniform spectral grid
  * w'_k = spec_lo + k (spec_hi - spec_lo)/(n_spec - 1), k < n_spec; Re chi0 at omega is the exact

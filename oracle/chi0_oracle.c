@@ -30,7 +30,7 @@
  *       = h[D_1, D_2, D_3, D_4, D_j],   h(x) = (w - x)^3 Log(w - x + i0),
  *
  * the 5-node divided difference with node j doubled (Hermite-Genocchi; the
- * paper states only that "a simpler set of integration formulas" applies to
+ * paper only says that simpler formulas become usable on
  * the final tetrahedra and does not print them).  Re is the principal value,
  * Im = -pi delta.  Divided differences are evaluated by the Newton recursion on
  * sorted nodes, except that any entry whose nodes cluster tightly compared with
