@@ -62,7 +62,8 @@ extern "C" {
 
 typedef enum chi0_status {
     CHI0_OK = 0,
-    CHI0_E_INVALID_ARG = -1,   /* null pointer, bad enum value, negative count */
+    CHI0_E_INVALID_ARG = -1,   /* null pointer, bad enum value, a count below its minimum (an empty q
+                                  list or frequency grid included): nothing is enqueued */
     CHI0_E_SHAPE = -2,         /* mesh, band, orbital or window sizes out of range */
     CHI0_E_NONFINITE = -3,     /* host values (mu, the spin factor, the degeneracy tolerances, q_frac,
                                   a spectral range) not finite; or, from the device scan, a

@@ -168,3 +168,51 @@ def test_degeneracy_tolerance_selects_the_fp64_near_branch():
         assert max_err(got, ref) <= 1e-5
     assert not np.array_equal(a, b)
     assert np.array_equal(b, c)        # both rules mark every final tetrahedron
+
+
+def test_empty_q_list_and_frequency_grid_are_rejected_at_every_entry_point():
+    """An empty q list or frequency grid is an invalid argument (CHI0_E_INVALID_ARG) at every entry
+    point that takes one: nothing is enqueued, the output keeps its contents, and the plan computes
+    as before afterwards."""
+    import ctypes
+    lib, torch, wl, plan, qs, om, eps, ck = _setup()
+    L, h = plan._lib, plan._h
+    nw = len(om)
+    ref = plan.dynamic(qs, om).cpu().numpy()
+    plan.sync()
+    arr = plan._qarray(qs)
+    ws = plan.workspace(1, nw)
+    wsp = plan.dynamic_pairs_workspace_bytes(1, nw)
+    ws = torch.empty(max(ws.numel(), wsp) + (1 << 20), dtype=torch.uint8, device=om.device)
+    wp, wn = ctypes.c_void_p(ws.data_ptr()), int(ws.numel())
+    nbw = plan.nbw
+    out = torch.full((nbw * nbw * nw * 2,), 7.0, dtype=torch.float64, device=om.device)
+    op, cp = ctypes.c_void_p(om.data_ptr()), ctypes.c_void_p(out.data_ptr())
+    sz = ctypes.c_size_t()
+    counts = (ctypes.c_uint64 * 7)(*([5] * 7))
+    calls = {
+        "workspace_size, nq = 0": lambda: L.chi0_workspace_size(h, 0, nw, ctypes.byref(sz)),
+        "workspace_size, nw = 0": lambda: L.chi0_workspace_size(h, 1, 0, ctypes.byref(sz)),
+        "pairs workspace_size, nw = 0": lambda: L.chi0_dynamic_pairs_workspace_size(h, 1, 0, ctypes.byref(sz)),
+        "kk workspace_size, nq = 0": lambda: L.chi0_kk_workspace_size(h, 0, nw, 64, ctypes.byref(sz)),
+        "static, nq = 0": lambda: L.chi0_static(h, 0, arr, wp, wn, cp),
+        "static_pairs, nq = 0": lambda: L.chi0_static_pairs(h, 0, arr, wp, wn, cp),
+        "dynamic, nq = 0": lambda: L.chi0_dynamic(h, 0, arr, nw, op, wp, wn, cp),
+        "dynamic, nw = 0": lambda: L.chi0_dynamic(h, 1, arr, 0, op, wp, wn, cp),
+        "dynamic_pairs, nq = 0": lambda: L.chi0_dynamic_pairs(h, 0, arr, nw, op, wp, wn, cp),
+        "dynamic_pairs, nw = 0": lambda: L.chi0_dynamic_pairs(h, 1, arr, 0, op, wp, wn, cp),
+        "dynamic_noalloc, nq = 0": lambda: L.chi0_dynamic_noalloc(h, 0, arr, nw, op, cp),
+        "dynamic_noalloc, nw = 0": lambda: L.chi0_dynamic_noalloc(h, 1, arr, 0, op, cp),
+        "dynamic_kk, nw = 0": lambda: L.chi0_dynamic_kk(h, 1, arr, 0, op, 64, -20.0, 20.0, wp, wn, cp),
+        "static_group, nq = 0": lambda: L.chi0_static_group(h, 0, 1, arr, wp, wn, cp),
+        "dynamic_group, nw = 0": lambda: L.chi0_dynamic_group(h, 1, 1, arr, 0, op, wp, wn, cp),
+        "census, nw = 0": lambda: L.chi0_census(h, 1, arr, 0, op, wp, wn, counts),
+    }
+    for what, call in calls.items():
+        _say("empty input:", what)
+        assert call() == -1, what
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all()) and list(counts) == [5] * 7
+    got = plan.dynamic(qs, om).cpu().numpy()
+    plan.sync()
+    assert np.array_equal(got, ref)
