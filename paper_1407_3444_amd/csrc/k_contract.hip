@@ -5,10 +5,12 @@
 // Per k this is a small complex GEMM (bands x orbitals) x (orbitals x bands); it
 // runs as real 16x16x4 FP64 MFMAs (v_mfma_f64_16x16x4f64), four per step of 4
 // orbitals:  Re M = Cr^T Br + Ci^T Bi,  Im M = Cr^T Bi - Ci^T Br.
-// A workgroup is one wave that handles 16 consecutive k; |M|^2 of a 16x16 band
-// tile is staged in LDS as [n][m][k] and written out pair-major, so each store
-// covers 16 consecutive k of one band pair (the layout the tetrahedron kernel
-// reads with consecutive lanes on consecutive cells).
+// A workgroup is one wave that handles 16 consecutive k, two at a time (their loads
+// in flight together); |M|^2 of a band tile (min(nbw, 16) squared pairs) is staged in
+// LDS as [pair][k] and written out pair-major, so each store covers 16 consecutive k
+// of one band pair (the layout the tetrahedron kernel reads with consecutive lanes on
+// consecutive cells).  The staging tile is sized for the band window at launch, so a
+// 10-band window holds 11 workgroups per CU rather than 4.
 #include "chi0_internal.h"
 
 namespace chi0 {
@@ -18,8 +20,12 @@ namespace {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKPerBlock = 16;
+constexpr int kHalfBlock = kKPerBlock / 2;   // the two k of one iteration: kl and kl + kHalfBlock
+constexpr int kTileLd = kKPerBlock + 1;      // staged values per pair (odd: no bank conflicts)
+constexpr int kXcd = 8;                      // XCDs; workgroup b is dispatched to XCD b % kXcd
 
-typedef double Tile[16][kKPerBlock + 1];
+// Band tile edge of the staging tile: the window itself up to 16 bands, else 16.
+__host__ __device__ inline int tile_dim(int nbw) { return nbw < 16 ? nbw : 16; }
 
 // Mesh index of k + q: the shifted mesh point, or k itself when the k+q data are given explicitly.
 __device__ __forceinline__ int64_t shifted_k(const MeshDev &M, const QDev &Q, int64_t k)
@@ -35,60 +41,85 @@ __device__ __forceinline__ int64_t shifted_k(const MeshDev &M, const QDev &Q, in
     return ((int64_t)i0 * M.n2 + i1) * M.n3 + i2;
 }
 
-// One workgroup of FP64 matrix elements: k = k0 .. k0+15 of one q.
-__device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &Q, int64_t k0, Tile *tile)
+// Stage |M|^2 of one k: accumulator element i of lane (g = lane / 16, row = lane % 16) is
+// D[g + 4 i][row] for the FP64 16x16x4 MFMA (F64) and D[4 g + i][row] for the 16x16x32 FP32-
+// accumulating ones (row index = band n, column = band m); pairs outside the T x T tile are padding.
+template <bool F64>
+__device__ __forceinline__ void stage_k(double *tile, int T, int g, int row, int kl, const double (&v)[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int n = F64 ? g + 4 * i : 4 * g + i;
+        if (n < T && row < T) tile[(n * T + row) * kTileLd + kl] = v[i];
+    }
+}
+
+// Write the staged tile (band tiles tn, tm) of k0 .. k0+15 pair-major into W: 16 consecutive
+// lanes store the 16 k of one pair.
+__device__ __forceinline__ void write_tile(const MeshDev &M, const QDev &Q, const double *tile, int T, int tn,
+                                           int tm, int64_t k0, int lane)
+{
+    for (int e = lane; e < T * T * kKPerBlock; e += 64) {
+        const int kl = e % kKPerBlock;
+        const int pj = e / kKPerBlock;
+        const int i = pj / T, j = pj - i * T;
+        const int nn = tn * 16 + i, mm = tm * 16 + j;
+        const int64_t k = k0 + kl;
+        if (nn < M.nbw && mm < M.nbw && k < M.nk) Q.W[((int64_t)nn * M.nbw + mm) * M.nk + k] = tile[pj * kTileLd + kl];
+    }
+}
+
+// One workgroup of FP64 matrix elements: k = k0 .. k0+15 of one q, as the pairs (kl, kl + 8).
+__device__ __forceinline__ void contract_f64_body(const MeshDev &M, const QDev &Q, int64_t k0, double *tile)
 {
     const int lane = threadIdx.x;
     const int row = lane & 15;      // A row (band n) / B column (band m) of this lane
     const int kk = lane >> 4;       // orbital within the step of 4
     const int64_t nk = M.nk;
-    const int ntile = (M.nbw + 15) / 16;
+    const int ntile = (M.nbw + 15) / 16, T = tile_dim(M.nbw);
     const int nb = M.nb, no = M.no;
 
     for (int tn = 0; tn < ntile; ++tn) {
         for (int tm = 0; tm < ntile; ++tm) {
             const int n = tn * 16 + row;
             const int m = tm * 16 + row;
-            for (int kl = 0; kl < kKPerBlock; ++kl) {
-                const int64_t k = k0 + kl;
-                if (k >= nk) break;
-                const int64_t kq = shifted_k(M, Q, k);
-                dbl4 accr = {0.0, 0.0, 0.0, 0.0};
-                dbl4 acci = {0.0, 0.0, 0.0, 0.0};
+            for (int kl = 0; kl < kHalfBlock; ++kl) {
+                const int64_t ka = k0 + kl, kb = ka + kHalfBlock;
+                if (ka >= nk) break;
+                const bool vb = kb < nk;
+                const int64_t kqa = shifted_k(M, Q, ka), kqb = vb ? shifted_k(M, Q, kb) : kqa;
+                dbl4 ra = {0.0, 0.0, 0.0, 0.0}, ia = ra, rb = ra, ib = ra;
                 for (int o0 = 0; o0 < no; o0 += 4) {
                     const int o = o0 + kk;
-                    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+                    double2 a0 = {0.0, 0.0}, a1 = a0, b0 = a0, b1 = a0;
                     if (o < no && n < M.nbw) {
-                        const double *p = M.c_k + 2 * ((k * no + o) * nb + M.lo + n);
-                        ar = p[0];
-                        ai = p[1];
+                        a0 = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((ka * no + o) * nb + M.lo + n));
+                        if (vb) a1 = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((kb * no + o) * nb + M.lo + n));
                     }
                     if (o < no && m < M.nbw) {
-                        const double *p = Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m);
-                        br = p[0];
-                        bi = p[1];
+                        b0 = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kqa * no + o) * nb + M.lo + m));
+                        if (vb) b1 = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kqb * no + o) * nb + M.lo + m));
                     }
-                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
-                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, accr, 0, 0, 0);
-                    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
-                    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, acci, 0, 0, 0);
+                    ra = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b0.x, ra, 0, 0, 0);
+                    rb = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1.x, rb, 0, 0, 0);
+                    ra = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b0.y, ra, 0, 0, 0);
+                    rb = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b1.y, rb, 0, 0, 0);
+                    ia = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b0.y, ia, 0, 0, 0);
+                    ib = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1.y, ib, 0, 0, 0);
+                    ia = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0.y, b0.x, ia, 0, 0, 0);
+                    ib = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1.y, b1.x, ib, 0, 0, 0);
                 }
-                // accumulator element v of this lane is D[kk + 4 v][row] (row index = band n,
-                // column = band m) for the FP64 16x16x4 MFMA
+                double va[4], vv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    tile[kk + 4 * v][row][kl] = accr[v] * accr[v] + acci[v] * acci[v];
+                for (int v = 0; v < 4; ++v) {
+                    va[v] = ra[v] * ra[v] + ia[v] * ia[v];
+                    vv[v] = rb[v] * rb[v] + ib[v] * ib[v];
+                }
+                stage_k<true>(tile, T, kk, row, kl, va);
+                if (vb) stage_k<true>(tile, T, kk, row, kl + kHalfBlock, vv);
             }
             __syncthreads();
-            for (int e = lane; e < 16 * 16 * kKPerBlock; e += 64) {
-                const int kl = e % kKPerBlock;
-                const int pj = e / kKPerBlock;
-                const int i = pj / 16, j = pj % 16;
-                const int nn = tn * 16 + i, mm = tm * 16 + j;
-                const int64_t k = k0 + kl;
-                if (nn < M.nbw && mm < M.nbw && k < nk)
-                    Q.W[((int64_t)nn * M.nbw + mm) * nk + k] = tile[i][j][kl];
-            }
+            write_tile(M, Q, tile, T, tn, tm, k0, lane);
             __syncthreads();
         }
     }
@@ -196,70 +227,104 @@ __device__ __forceinline__ double split_abs2(const SplitAcc &c, int v)
     return mr * mr + mi * mi;
 }
 
-// One workgroup of split-precision matrix elements: k = k0 .. k0+15 of one q.
+// One workgroup of split-precision matrix elements: k = k0 .. k0+15 of one q, as the pairs
+// (kl, kl + 8).
 template <bool FP16>
-__device__ __forceinline__ void contract_split_body(const MeshDev &M, const QDev &Q, int64_t k0, Tile *tile)
+__device__ __forceinline__ void contract_split_body(const MeshDev &M, const QDev &Q, int64_t k0, double *tile)
 {
     const int lane = threadIdx.x;
     const int row = lane & 15;      // A row (band n) / B column (band m)
     const int g = lane >> 4;        // orbitals 4g .. 4g+3 of a step of 16
     const int64_t nk = M.nk;
-    const int ntile = (M.nbw + 15) / 16;
+    const int ntile = (M.nbw + 15) / 16, T = tile_dim(M.nbw);
     const int nb = M.nb, no = M.no;
 
     for (int tn = 0; tn < ntile; ++tn) {
         for (int tm = 0; tm < ntile; ++tm) {
             const int n = tn * 16 + row;
             const int m = tm * 16 + row;
-            for (int kl = 0; kl < kKPerBlock; ++kl) {
-                const int64_t k = k0 + kl;
-                if (k >= nk) break;
-                const int64_t kq = shifted_k(M, Q, k);
-                SplitAcc acc;
-                acc.re = acc.re_c = acc.im = acc.im_c = flt4{0.f, 0.f, 0.f, 0.f};
+            for (int kl = 0; kl < kHalfBlock; ++kl) {
+                const int64_t ka = k0 + kl, kb = ka + kHalfBlock;
+                if (ka >= nk) break;
+                const bool vb = kb < nk;
+                const int64_t kqa = shifted_k(M, Q, ka), kqb = vb ? shifted_k(M, Q, kb) : kqa;
+                SplitAcc acc0, acc1;
+                acc0.re = acc0.re_c = acc0.im = acc0.im_c = flt4{0.f, 0.f, 0.f, 0.f};
+                acc1 = acc0;
                 for (int o0 = 0; o0 < no; o0 += 16) {
-                    double2 av[4], bv[4];
+                    double2 av0[4], bv0[4], av1[4], bv1[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int o = o0 + 4 * g + i;
-                        av[i] = bv[i] = double2{0.0, 0.0};
-                        if (o < no && n < M.nbw) av[i] = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((k * no + o) * nb + M.lo + n));
-                        if (o < no && m < M.nbw) bv[i] = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kq * no + o) * nb + M.lo + m));
+                        av0[i] = bv0[i] = av1[i] = bv1[i] = double2{0.0, 0.0};
+                        if (o < no && n < M.nbw) {
+                            av0[i] = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((ka * no + o) * nb + M.lo + n));
+                            if (vb) av1[i] = *reinterpret_cast<const double2 *>(M.c_k + 2 * ((kb * no + o) * nb + M.lo + n));
+                        }
+                        if (o < no && m < M.nbw) {
+                            bv0[i] = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kqa * no + o) * nb + M.lo + m));
+                            if (vb) bv1[i] = *reinterpret_cast<const double2 *>(Q.c_kq + 2 * ((kqb * no + o) * nb + M.lo + m));
+                        }
                     }
                     u32x4 ah, al, bh, bl;
-                    split_op<FP16>(av, ah, al);
-                    split_op<FP16>(bv, bh, bl);
-                    split_step<FP16>(acc, ah, al, bh, bl);
+                    split_op<FP16>(av0, ah, al);
+                    split_op<FP16>(bv0, bh, bl);
+                    split_step<FP16>(acc0, ah, al, bh, bl);
+                    split_op<FP16>(av1, ah, al);
+                    split_op<FP16>(bv1, bh, bl);
+                    split_step<FP16>(acc1, ah, al, bh, bl);
                 }
-                // accumulator element v of this lane is D[4 g + v][row] for the 16x16 MFMAs
+                double va[4], vv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) tile[4 * g + v][row][kl] = split_abs2<FP16>(acc, v);
+                for (int v = 0; v < 4; ++v) {
+                    va[v] = split_abs2<FP16>(acc0, v);
+                    vv[v] = split_abs2<FP16>(acc1, v);
+                }
+                stage_k<false>(tile, T, g, row, kl, va);
+                if (vb) stage_k<false>(tile, T, g, row, kl + kHalfBlock, vv);
             }
             __syncthreads();
-            for (int e = lane; e < 16 * 16 * kKPerBlock; e += 64) {
-                const int kl = e % kKPerBlock;
-                const int pj = e / kKPerBlock;
-                const int i = pj / 16, j = pj % 16;
-                const int nn = tn * 16 + i, mm = tm * 16 + j;
-                const int64_t k = k0 + kl;
-                if (nn < M.nbw && mm < M.nbw && k < nk) Q.W[((int64_t)nn * M.nbw + mm) * nk + k] = tile[i][j][kl];
-            }
+            write_tile(M, Q, tile, T, tn, tm, k0, lane);
             __syncthreads();
         }
     }
 }
 
-__global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B)
+// The (k-block, q) of a small-basis workgroup.  The launch is 1-D; workgroup b runs on XCD
+// b % kXcd, each XCD takes a contiguous range of k-blocks, and the q of one k-block sit on
+// consecutive slots of one XCD, so C(k) is fetched from HBM once and shared by the q in that XCD's
+// L2.  False past the last k-block (the whole workgroup returns before any barrier).
+__device__ __forceinline__ bool small_item(const MeshDev &M, int nq, int64_t &k0, int &qi)
 {
-    __shared__ double tile[16][16][kKPerBlock + 1];
-    contract_f64_body(M, B.q[blockIdx.y], (int64_t)blockIdx.x * kKPerBlock, tile);
+    const int64_t nkb = (M.nk + kKPerBlock - 1) / kKPerBlock;
+    const int64_t b = blockIdx.x;
+    const int xcd = (int)(b % kXcd);
+    const int64_t slot = b / kXcd;
+    const int64_t per_xcd = (nkb + kXcd - 1) / kXcd;
+    const int64_t kb = xcd * per_xcd + slot / nq;
+    qi = (int)(slot % nq);
+    k0 = kb * kKPerBlock;
+    return kb < nkb;
+}
+
+// Dynamic LDS: the staging tile, tile_dim(nbw)^2 * kTileLd doubles.
+__global__ __launch_bounds__(64) void contract_f64_kernel(MeshDev M, BatchDev B, int nq)
+{
+    extern __shared__ double tile[];
+    int64_t k0;
+    int qi;
+    if (!small_item(M, nq, k0, qi)) return;
+    contract_f64_body(M, B.q[qi], k0, tile);
 }
 
 template <bool FP16>
-__global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev B)
+__global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev B, int nq)
 {
-    __shared__ double tile[16][16][kKPerBlock + 1];
-    contract_split_body<FP16>(M, B.q[blockIdx.y], (int64_t)blockIdx.x * kKPerBlock, tile);
+    extern __shared__ double tile[];
+    int64_t k0;
+    int qi;
+    if (!small_item(M, nq, k0, qi)) return;
+    contract_split_body<FP16>(M, B.q[qi], k0, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +348,6 @@ __global__ __launch_bounds__(64) void contract_split_kernel(MeshDev M, BatchDev 
 // which merges them into whole sectors.
 // ---------------------------------------------------------------------------
 constexpr int kPwQ = 8;      // q (waves) per workgroup
-constexpr int kXcd = 8;
 constexpr int kPwDepth = 4;  // steps of operands in flight per wave
 
 // The (k, q) of this wave; false past the mesh or the last q.  blockDim.x / 64 q per workgroup
@@ -592,7 +656,7 @@ __global__ __launch_bounds__(64 * kPwQ) void contract_pw_packed_kernel(MeshDev M
 __global__ __launch_bounds__(64) void contract_batch_kernel(const BatchItemDev *__restrict__ items,
                                                             const int32_t *__restrict__ block_item)
 {
-    __shared__ double tile[16][16][kKPerBlock + 1];
+    __shared__ double tile[16 * 16 * kTileLd];
     const BatchItemDev it = items[block_item[blockIdx.x]];
     const int64_t k0 = (int64_t)(blockIdx.x - it.ka_begin) * kKPerBlock;
     if (it.precision == 1)
@@ -663,14 +727,18 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
         }
         return hipGetLastError();
     }
-    const int64_t nblk = (mesh.nk + kKPerBlock - 1) / kKPerBlock;
-    dim3 grid((unsigned)nblk, nq), block(64);
+    const int64_t nkb = (mesh.nk + kKPerBlock - 1) / kKPerBlock;
+    const int64_t nblk = (nkb + kXcd - 1) / kXcd * kXcd * nq;
+    if (nblk >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    const int T = tile_dim(mesh.nbw);
+    const size_t lds = (size_t)T * T * kTileLd * sizeof(double);
+    const dim3 grid((unsigned)nblk), block(64);
     if (precision == 1)
-        hipLaunchKernelGGL(contract_split_kernel<false>, grid, block, 0, s, mesh, batch);
+        hipLaunchKernelGGL(contract_split_kernel<false>, grid, block, lds, s, mesh, batch, nq);
     else if (precision == 2)
-        hipLaunchKernelGGL(contract_split_kernel<true>, grid, block, 0, s, mesh, batch);
+        hipLaunchKernelGGL(contract_split_kernel<true>, grid, block, lds, s, mesh, batch, nq);
     else
-        hipLaunchKernelGGL(contract_f64_kernel, grid, block, 0, s, mesh, batch);
+        hipLaunchKernelGGL(contract_f64_kernel, grid, block, lds, s, mesh, batch, nq);
     return hipGetLastError();
 }
 
