@@ -141,7 +141,9 @@ chi0_status chi0_plan(chi0_plan_t *out, const chi0_desc *desc, const double *eps
  * the q of one launch sequence (batch_hint) and, for a split-precision plan with a basis above 64
  * whose launches take 3 or more q, the eigenvectors of the band window split once into 16-bit
  * high and low parts (8 bytes per coefficient): launches whose q are all mesh shifts read those
- * instead of the FP64 coefficients. */
+ * instead of the FP64 coefficients.  It also holds each window band's energy range over the
+ * k-points (e(k) and every e(k+q) of a launch), from which the tetrahedron kernels skip the band
+ * pairs that have no carved region anywhere (no change to any result). */
 chi0_status chi0_workspace_size(chi0_plan_t plan, int32_t nq, int32_t nw, size_t *bytes);
 
 /* Static chi0(q, 0) (Sec. III uses Eq. (1) at w = 0, where Im vanishes).

@@ -208,9 +208,16 @@ int n_blocks_pair(const chi0_plan_s *p)
 }
 
 struct Layout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, pack_off, pack_bytes, count_off, flag_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, pack_off, pack_bytes, count_off, flag_off, rng_off,
+        rng_bytes, total;
     int qbatch;
 };
+
+// The band ranges of a q batch (e(k), then each q's e(k+q)): [1 + qbatch][nbw][2] doubles.
+size_t range_bytes(const chi0_plan_s *p, int qbatch)
+{
+    return align_up(sizeof(double) * 2 * (size_t)p->mesh.nbw * (size_t)(1 + qbatch));
+}
 
 // qcap > 0 caps the q-points per launch sequence below the plan's own (the no-allocation call);
 // packed: room for the split operands of a split-precision plane-wave plan whose launches take
@@ -232,7 +239,9 @@ Layout layout(const chi0_plan_s *p, int nq, int nvals, int qcap = 0, bool packed
                        : 0;
     L.count_off = L.pack_off + L.pack_bytes;
     L.flag_off = L.count_off + 128;       // census counters (56 bytes), then the scan verdict
-    L.total = L.count_off + kAlign;
+    L.rng_off = L.count_off + kAlign;
+    L.rng_bytes = range_bytes(p, L.qbatch);
+    L.total = L.rng_off + L.rng_bytes;
     return L;
 }
 
@@ -251,7 +260,7 @@ unsigned *scan_flag(void *ws, const Layout &L)
 // kMaxOmegaIm frequencies per launch), then the frequency list (grid and requested) and the
 // imaginary part on it for one batch of q.
 struct KKLayout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, om_off, im_off, flag_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, om_off, im_off, flag_off, rng_off, rng_bytes, total;
     int qbatch, n_all;
 };
 
@@ -267,14 +276,16 @@ KKLayout kk_layout(const chi0_plan_s *p, int nq, int nw, int K)
     L.om_off = L.part_off + L.part_bytes_per_q * L.qbatch;
     L.im_off = L.om_off + align_up(sizeof(double) * (size_t)L.n_all);
     L.flag_off = L.im_off + align_up(sizeof(double) * 2 * (size_t)L.n_all * L.qbatch);
-    L.total = L.flag_off + kAlign;
+    L.rng_off = L.flag_off + kAlign;
+    L.rng_bytes = range_bytes(p, L.qbatch);
+    L.total = L.rng_off + L.rng_bytes;
     return L;
 }
 
 // Workspace of the pair-resolved dynamic call: W of one q batch, then the partial sums
 // [q][pair][nblk][2 nwc] (nblk workgroups per pair), then the scan verdict.
 struct PairsLayout {
-    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, flag_off, total;
+    size_t w_off, w_bytes_per_q, part_off, part_bytes_per_q, flag_off, rng_off, rng_bytes, total;
     int qbatch, nblk;
 };
 
@@ -295,7 +306,9 @@ PairsLayout dpairs_layout(const chi0_plan_s *p, int nq, int nvals)
     L.w_off = 0;
     L.part_off = L.w_bytes_per_q * L.qbatch;
     L.flag_off = L.part_off + L.part_bytes_per_q * L.qbatch;
-    L.total = L.flag_off + kAlign;
+    L.rng_off = L.flag_off + kAlign;
+    L.rng_bytes = range_bytes(p, L.qbatch);
+    L.total = L.rng_off + L.rng_bytes;
     return L;
 }
 
@@ -336,13 +349,20 @@ std::vector<GroupLaunch> group_launches(int nq, int n_group, int qbatch)
     return out;
 }
 
+// The device descriptors of q0 .. q0 + nqb - 1: W of q i in the workspace's W region, and, when the
+// layout has one, the band ranges in its range region (e(k) first, then q i's e(k+q)).
 void fill_batch(const chi0_plan_s *p, const chi0_q *qs, int q0, int nqb, void *ws, const Layout &L, BatchDev &B)
 {
     std::memset(&B, 0, sizeof B);
+    double *rng = L.rng_bytes ? reinterpret_cast<double *>(static_cast<char *>(ws) + L.rng_off) : nullptr;
     for (int i = 0; i < nqb; ++i) {
         double *W = p->d.cma ? nullptr
                              : reinterpret_cast<double *>(static_cast<char *>(ws) + L.w_off + L.w_bytes_per_q * i);
         B.q[i] = make_qdev(p->mesh, qs[q0 + i], W);
+        if (rng) {
+            B.q[i].rng_k = rng;
+            B.q[i].rng_kq = rng + 2 * (size_t)p->mesh.nbw * (1 + i);
+        }
     }
 }
 
@@ -849,6 +869,8 @@ chi0_status chi0_dynamic_pairs(chi0_plan_t p, int32_t nq, const chi0_q *qs, int3
     Layout Lw = {};   // W of the batch at the start of the workspace, as for chi0_dynamic
     Lw.w_off = L.w_off;
     Lw.w_bytes_per_q = L.w_bytes_per_q;
+    Lw.rng_off = L.rng_off;
+    Lw.rng_bytes = L.rng_bytes;
     PackState pk = {nullptr, false};
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
@@ -916,6 +938,8 @@ chi0_status chi0_dynamic_kk(chi0_plan_t p, int32_t nq, const chi0_q *qs, int32_t
     Layout Lw = {};   // W of the batch sits at the start of the workspace, as for chi0_dynamic
     Lw.w_off = L.w_off;
     Lw.w_bytes_per_q = L.w_bytes_per_q;
+    Lw.rng_off = L.rng_off;
+    Lw.rng_bytes = L.rng_bytes;
     PackState pk = pack_state(ws, Lw);
     for (int q0 = 0; q0 < nq; q0 += L.qbatch) {
         const int nqb = std::min(L.qbatch, nq - q0);
@@ -1040,7 +1064,8 @@ chi0_status chi0_matrix_elements(chi0_plan_t p, const chi0_q *q, double *W)
     st = check_qs(p, 1, q);
     if (st) return st;
     if (!W) return fail(p, CHI0_E_INVALID_ARG, "W is null");
-    Layout L = layout(p, 1, 1);
+    Layout L = {};    // W itself is the W region of q 0 (no other region)
+    L.w_bytes_per_q = layout(p, 1, 1).w_bytes_per_q;
     BatchDev B;
     fill_batch(p, q, 0, 1, W, L, B);
     hipError_t e = launch_contract(p->mesh, B, 1, p->d.precision, nullptr, p->stream);

@@ -22,6 +22,12 @@ struct QDev {
     double *W;              // [nbw][nbw][Nk] matrix elements of this q (null under CMA)
     int32_t shift[3];       // mesh shift (0 in explicit mode)
     int32_t explicit_kq;
+    // Band ranges over all k-points of the arrays, [nbw][2] = (min, max) of the window's bands:
+    // e(k) (shared by the q of a batch) and this q's e(k+q); filled by launch_band_range ahead of
+    // the tetrahedron kernels, which then skip rounds of band pairs with no carved region.  Null:
+    // no skipping.
+    double *rng_k;
+    double *rng_kq;
 };
 
 struct BatchDev {
@@ -87,6 +93,10 @@ hipError_t launch_contract(const MeshDev &mesh, const BatchDev &batch, int nq, i
                            hipStream_t s);
 constexpr int kPackMinQ = 3;
 size_t pack_bytes(const MeshDev &mesh);
+
+// Band ranges of a batch (see QDev::rng_k): nothing when the batch carries no range pointers.
+// Every K_B launcher below calls it before its kernel.
+hipError_t launch_band_range(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s);
 
 // K_B static: per-block partial sums of Re chi0(q, 0) (unnormalised) into partial[nq][nblocks].
 hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, double *partial,

@@ -292,6 +292,54 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
+// Band pairs with a carved region somewhere on the mesh, one bit per pair index p = n nbw + m < 256:
+// region 1 = {e < mu < e'} needs some e_n < mu and some e'_m > mu, region 2 the reverse, and the
+// band ranges run over every k-point of the arrays.  Without ranges, or with more than 256 pairs,
+// every pair is marked.  Built once per workgroup (one ballot per 64 pairs).
+struct PairMask {
+    uint64_t bits[4];
+    __device__ __forceinline__ bool active(int p) const
+    {
+        const int w = p >> 6;
+        const uint64_t b = w == 0 ? bits[0] : w == 1 ? bits[1] : w == 2 ? bits[2] : bits[3];
+        return ((b >> (p & 63)) & 1) != 0;
+    }
+};
+
+__device__ __forceinline__ PairMask pair_mask(const MeshDev &M, const QDev &Q, int lane)
+{
+    PairMask pm;
+    const int npairs = M.nbw * M.nbw;
+    const bool use = Q.rng_k != nullptr && npairs <= 4 * kWave;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = lane + kWave * j;
+        bool a = true;
+        if (use && p < npairs) {
+            const int n = p / M.nbw, m = p - n * M.nbw;
+            a = (Q.rng_k[2 * n] < M.mu && Q.rng_kq[2 * m + 1] > M.mu) ||
+                (Q.rng_k[2 * n + 1] > M.mu && Q.rng_kq[2 * m] < M.mu);
+        }
+        pm.bits[j] = __ballot(a);
+    }
+    return pm;
+}
+
+// True when the round of 64 units starting at b0 touches only pairs with no carved region: its
+// own pair and, when it runs past that pair's last unit, the next one (a pair holds at least 64
+// units, else nothing is skipped).  Such units count no final tetrahedron, so skipping the round,
+// its loads included, leaves every result unchanged.  Wave-uniform.
+template <bool LIST>
+__device__ __forceinline__ bool round_inert(const MeshDev &M, const PairMask &pm, const UnitIdx &b0)
+{
+    if (b0.pair >= 4 * kWave || pm.active(b0.pair)) return false;
+    const int64_t per_pair = tets_per_pair(M);
+    const int64_t off = (int64_t)b0.perm * n_cells<LIST>(M) + b0.cell;     // unit offset in the pair
+    if (off + kWave <= per_pair) return true;
+    if (per_pair < kWave || b0.pair + 1 >= 4 * kWave) return false;
+    return !pm.active(b0.pair + 1);
+}
+
 __device__ __forceinline__ int wave_sum(int x)
 {
 #pragma unroll
@@ -460,12 +508,15 @@ __device__ __forceinline__ void dynamic_body(const MeshDev &M, const QDev &Q, in
     }
     wlo = wave_min(wlo);
     whi = wave_max(whi);
+    const PairMask pm = pair_mask(M, Q, lane);
     int qn = 0, qn32 = 0;      // this lane's FP64 and FP32 near items queued
 
     // rounds of 64 consecutive units, dealt to the workgroups round-robin: every workgroup
     // samples all band pairs, so the work per workgroup is even
     for (int64_t base = u0 + (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
+        const UnitIdx b0 = decode_unit<LIST>(M, base);
+        if (round_inert<LIST>(M, pm, b0)) continue;
+        const UnitIdx ux = round_unit<LIST>(M, b0, lane);
         const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
@@ -720,8 +771,11 @@ __device__ __forceinline__ double static_body(const MeshDev &M, const QDev &Q, i
 {
     const int lane = threadIdx.x;
     double acc = 0.0;
+    const PairMask pm = pair_mask(M, Q, lane);
     for (int64_t base = u0 + (int64_t)blk * kWave; base < u1; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
+        const UnitIdx b0 = decode_unit<LIST>(M, base);
+        if (round_inert<LIST>(M, pm, b0)) continue;
+        const UnitIdx ux = round_unit<LIST>(M, b0, lane);
         const bool valid = base + lane < u1;
         int cnt = 0;
         if (valid) {

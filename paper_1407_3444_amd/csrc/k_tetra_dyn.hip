@@ -8,6 +8,7 @@ hipError_t launch_tetra_dynamic(const MeshDev &mesh, const BatchDev &batch, int 
                                 const double *omega, int nw, double *partial, bool mixed, hipStream_t s)
 {
     if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     dim3 grid(nblocks, nq), block(kWave);
     int slots = (nw + kWave - 1) / kWave;
     if (mesh.tets) return launch_tetra_dynamic_list(mesh, batch, nq, nblocks, omega, nw, partial, mixed, s);
@@ -33,6 +34,7 @@ hipError_t launch_tetra_dynamic_pairs(const MeshDev &mesh, const BatchDev &batch
 {
     if (nw < 1 || nw > kMaxOmegaPerLaunch || nq < 1 || nq > kMaxQBatch || nblk < 1 || mesh.tets)
         return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     const int64_t nx = (int64_t)mesh.nbw * mesh.nbw * nblk;
     if (nx >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     dim3 grid((unsigned)nx, nq), block(kWave);

@@ -78,8 +78,11 @@ __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int
     wlo = wave_min(wlo);
     whi = wave_max(whi);
     int qn = 0;
+    const PairMask pm = pair_mask(M, Q, lane);
     for (int64_t base = (int64_t)blk * kWave; base < n_units; base += (int64_t)nblocks * kWave) {
-        const UnitIdx ux = round_unit<LIST>(M, decode_unit<LIST>(M, base), lane);
+        const UnitIdx b0 = decode_unit<LIST>(M, base);
+        if (round_inert<LIST>(M, pm, b0)) continue;
+        const UnitIdx ux = round_unit<LIST>(M, b0, lane);
         const bool valid = base + lane < n_units;
         int cnt = 0;
         if (valid) {
@@ -174,13 +177,56 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
     }
 }
 
+// Minimum and maximum of each window band's energies over all k-points of the arrays: workgroup
+// (b, 0) reduces band b of e(k) into rng_k, workgroup (b, 1 + i) band b of q i's e(k+q) into its
+// rng_kq (a mesh shift reads the plan's own energies).  NaN values are passed over.
+constexpr int kRangeThreads = 256;
+__global__ __launch_bounds__(kRangeThreads) void band_range_kernel(MeshDev M, BatchDev B)
+{
+    const int b = blockIdx.x, src = blockIdx.y;
+    const double *e = (src == 0 ? M.eps_k : B.q[src - 1].eps_kq) + (int64_t)(M.lo + b) * M.nk;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t k = threadIdx.x; k < M.nk; k += kRangeThreads) {
+        const double v = e[k];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    __shared__ double slo[kRangeThreads / kWave], shi[kRangeThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        slo[w] = lo;
+        shi[w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kRangeThreads / kWave; ++i) {
+            lo = fmin(lo, slo[i]);
+            hi = fmax(hi, shi[i]);
+        }
+        double *out = src == 0 ? B.q[0].rng_k : B.q[src - 1].rng_kq;
+        out[2 * b] = lo;
+        out[2 * b + 1] = hi;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_band_range(const MeshDev &mesh, const BatchDev &batch, int nq, hipStream_t s)
+{
+    if (!batch.q[0].rng_k) return hipSuccess;
+    if (nq < 1 || nq > kMaxQBatch || mesh.nbw < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(band_range_kernel, dim3(mesh.nbw, nq + 1), dim3(kRangeThreads), 0, s, mesh, batch);
+    return hipGetLastError();
+}
 
 hipError_t launch_census(const MeshDev &mesh, const BatchDev &batch, int nq, int nblocks, const double *omega,
                          int nw, double *partial, bool mixed, bool first_chunk, unsigned long long *counts,
                          hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch || nw < 1 || nw > kMaxOmegaPerLaunch || nblocks < 1) return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     dim3 grid(nblocks, nq), block(kWave);
     const int ct = first_chunk ? 1 : 0;
     if (mesh.tets) {
@@ -205,6 +251,7 @@ hipError_t launch_tetra_im(const MeshDev &mesh, const BatchDev &batch, int nq, i
                            int nw, double *partial, hipStream_t s)
 {
     if (nw < 1 || nw > kMaxOmegaIm || nq < 1 || nq > kMaxQBatch || nblocks < 1) return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     dim3 grid(nblocks, nq), block(kWave);
     const bool list = mesh.tets != nullptr;
     if (nw <= 8 * kWave) {
@@ -225,6 +272,7 @@ hipError_t launch_tetra_static_pairs(const MeshDev &mesh, const BatchDev &batch,
                                      hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch || nblk < 1) return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     dim3 grid(nblk * mesh.nbw * mesh.nbw, nq), block(kWave);
     if (mesh.tets)
         hipLaunchKernelGGL(tetra_static_pairs_kernel<true>, grid, block, 0, s, mesh, batch, nblk, partial);
@@ -237,6 +285,7 @@ hipError_t launch_tetra_static(const MeshDev &mesh, const BatchDev &batch, int n
                                hipStream_t s)
 {
     if (nq < 1 || nq > kMaxQBatch) return hipErrorInvalidValue;
+    if (hipError_t e = launch_band_range(mesh, batch, nq, s); e != hipSuccess) return e;
     dim3 grid(nblocks, nq), block(kWave);
     if (mesh.tets)
         hipLaunchKernelGGL(tetra_static_kernel<true>, grid, block, 0, s, mesh, batch, nblocks, partial);
