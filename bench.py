@@ -457,12 +457,10 @@ def bench_iw(args):
     qs = [lib.Q(eps_kq=torch.from_numpy(a).to(dev), c_kq=torch.from_numpy(b).to(dev)) for a, b in entries]
     ws = plan.workspace(len(qs), nw)
     out = torch.empty((len(q_list), nw, 2), dtype=torch.float64, device=dev)
-    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0,
-              "near_redo": 0}
+    census = {}
     for i in range(0, len(qs), 16):
-        cz = plan.census(qs[i:i + 16], om, workspace=ws)
-        for k in census:
-            census[k] += cz[k]
+        for k, v in plan.census(qs[i:i + 16], om, workspace=ws).items():
+            census[k] = census.get(k, 0) + v
     stream = torch.cuda.current_stream()
 
     def timed(fn, steps):
@@ -582,12 +580,10 @@ def bench_batch(args):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     seq_out = [torch.empty((len(i.qs), int(i.omega.shape[0]), 2), dtype=torch.float64, device=dev)
                for i in insts]
-    census = {"active_units": 0, "final_tetrahedra": 0, "near_evals": 0, "far_evals": 0, "far_terms": 0,
-              "near_redo": 0}
+    census = {}
     for p, i in zip(plans, insts):
-        c = p.census(i.qs, i.omega, workspace=ws)
-        for k in census:
-            census[k] += c[k]
+        for k, v in p.census(i.qs, i.omega, workspace=ws).items():
+            census[k] = census.get(k, 0) + v
     log("census", census)
 
     def seq():

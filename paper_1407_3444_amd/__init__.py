@@ -16,6 +16,10 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+# The counts of chi0_census, in the order of its counts[] array.
+CENSUS_KEYS = ("active_units", "final_tetrahedra", "near_evals", "far_evals", "far_terms", "near_redo",
+               "coef_terms")
+
 __all__ = ["Chi0Plan", "Chi0Batch", "Instance", "Q", "Chi0Error", "load_library", "LIB_PATH", "iw_cubic",
            "EXPORTED_SYMBOLS"]
 
@@ -479,11 +483,9 @@ class Chi0Plan:
         nw, op = self._omega(omega)
         arr = self._qarray(qs)
         ws, (wp, wn) = self._ws(workspace, nq, nw)
-        counts = (ctypes.c_uint64 * 7)()
+        counts = (ctypes.c_uint64 * len(CENSUS_KEYS))()
         self._check(self._lib.chi0_census(self._h, nq, arr, nw, op, wp, wn, counts), "chi0_census")
-        return {"active_units": int(counts[0]), "final_tetrahedra": int(counts[1]),
-                "near_evals": int(counts[2]), "far_evals": int(counts[3]), "far_terms": int(counts[4]),
-                "near_redo": int(counts[5]), "coef_terms": int(counts[6])}
+        return {k: int(counts[i]) for i, k in enumerate(CENSUS_KEYS)}
 
 
 def iw_cubic(n: int):
