@@ -145,9 +145,9 @@ def timed_median(fn, reps: int = 3):
 # The same for the plane-wave contraction kernel on the pw_static workload (16 q per launch), and
 # for the split forms' pair of kernels (the split into packed operands, then the packed-operand
 # contraction; figures of the BF16x3 pair, FP16x3 reads 5% less).
-PW_TRAFFIC_KERNEL_SHA = "20e7723c0483e551"
-PW_TRAFFIC_BYTES_PER_LAUNCH = (33376022 * 2.0 + 722177 * 1.0) * 1024
-PW_PACKED_TRAFFIC_BYTES_PER_LAUNCH = ((1769507 + 16824486) * 2.0 + (1769847 + 745282) * 1.0) * 1024
+PW_TRAFFIC_KERNEL_SHA = "34b23f18bec6d0d5"
+PW_TRAFFIC_BYTES_PER_LAUNCH = (33183559 * 2.0 + 700292 * 1.0) * 1024
+PW_PACKED_TRAFFIC_BYTES_PER_LAUNCH = ((1769503 + 16849096) * 2.0 + (1769824 + 754128) * 1.0) * 1024
 
 
 def kernel_sha(files=("k_tetra.h", "k_tetra_dyn.hip", "chi0_math.h")) -> str:
