@@ -10,8 +10,12 @@
 //     over its groups' k-tiles, one K_B launch over its items' workgroups, one K_R launch;
 //   * inside a stage the K_B workgroups are ordered by decreasing cost per workgroup, so the
 //     hardware dispatcher hands out the longest work first (longest-job-first without a
-//     device queue, and deterministic: every workgroup owns a fixed slice of partial sums).
-// Workspace: [item table | K_A, K_B, K_R block->item tables | W arena | partial-sum arena].
+//     device queue, and deterministic: every workgroup owns a fixed slice of partial sums);
+//   * before its K_B launch a stage takes the band ranges of its groups (e(k) and e(k+q) of each
+//     window band), from which K_B skips the band pairs with no carved region, as the single-plan
+//     calls do.
+// Workspace: [item table | K_A, K_B, K_R block->item tables and group->item tables |
+//             W arena | partial-sum arena | band ranges of every group].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,14 +50,16 @@ struct Item {
 struct Stage {
     std::vector<int> groups;     // (instance, q) group indices, K_A order
     std::vector<int> items;      // item indices, K_B order
-    int64_t blocks[3];           // K_A, K_B, K_R workgroups
-    size_t table_off[3];         // byte offsets of the block->item tables in the workspace
+    int64_t blocks[4];           // K_A, K_B, K_R workgroups; groups (band-range jobs)
+    size_t table_off[4];         // byte offsets of the block->item and group->item tables
     size_t w_bytes, part_bytes;
+    int max_nbw;                 // widest band window of the stage's groups
 };
 
 struct Group {
     int inst, q;
     size_t w_bytes;
+    size_t rng_off;              // this group's band ranges in the range arena: [2][nbw][2] doubles
     double cost;
     std::vector<int> items;
 };
@@ -62,7 +68,7 @@ struct Schedule {
     std::vector<Item> items;
     std::vector<Group> groups;
     std::vector<Stage> stages;
-    size_t items_off, w_off, part_off, total;
+    size_t items_off, w_off, part_off, rng_off, total;
     int64_t blocks_total[3];
 };
 
@@ -136,6 +142,7 @@ Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64
             g.inst = i;
             g.q = j;
             g.w_bytes = M.cma ? 0 : align_up(sizeof(double) * (size_t)M.nbw * M.nbw * M.nk);
+            g.rng_off = 0;
             g.cost = 0.0;
             for (int w0 = 0; w0 < inst[i].in.nw; w0 += chunk) {
                 Item it;
@@ -184,10 +191,13 @@ Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64
     size_t max_w = 0, max_part = 0;
     for (Stage &st : S.stages) {
         st.blocks[0] = st.blocks[1] = st.blocks[2] = 0;
+        st.blocks[3] = (int64_t)st.groups.size();
         st.part_bytes = 0;
+        st.max_nbw = 1;
         for (int gi : st.groups) {
             const Group &g = S.groups[gi];
             const MeshDev &M = inst[g.inst].mesh;
+            st.max_nbw = std::max(st.max_nbw, (int)M.nbw);
             if (!M.cma) st.blocks[0] += (M.nk + kKTile - 1) / kKTile;
             for (int ii : g.items) {
                 st.items.push_back(ii);
@@ -200,36 +210,46 @@ Schedule make_schedule(const std::vector<Inst> &inst, int64_t workgroups, uint64
         std::stable_sort(st.items.begin(), st.items.end(), [&](int a, int b) {
             return S.items[a].cost / S.items[a].nblocks > S.items[b].cost / S.items[b].nblocks;
         });
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             st.table_off[k] = off;
             off += align_up(sizeof(int32_t) * (size_t)st.blocks[k]);
-            S.blocks_total[k] += st.blocks[k];
+            if (k < 3) S.blocks_total[k] += st.blocks[k];
         }
         max_w = std::max(max_w, st.w_bytes);
         max_part = std::max(max_part, st.part_bytes);
     }
     S.w_off = off;
     S.part_off = S.w_off + max_w;
-    S.total = S.part_off + max_part;
+    S.rng_off = S.part_off + max_part;
+    size_t rng = 0;
+    for (Group &g : S.groups) {
+        g.rng_off = rng;
+        rng += align_up(sizeof(double) * 4 * (size_t)inst[g.inst].mesh.nbw);
+    }
+    S.total = S.rng_off + rng;
     return S;
 }
 
-// Host images of the item table and the three block tables of every stage.
+// Host images of the item table and the four tables of every stage.
 void build_tables(const std::vector<Inst> &inst, const Schedule &S, char *ws, std::vector<BatchItemDev> &items,
                   std::vector<std::vector<int32_t>> &tables)
 {
     items.assign(S.items.size(), BatchItemDev{});
-    tables.assign(3 * S.stages.size(), {});
+    tables.assign(4 * S.stages.size(), {});
     for (size_t si = 0; si < S.stages.size(); ++si) {
         const Stage &st = S.stages[si];
-        std::vector<int32_t> &ta = tables[3 * si], &tb = tables[3 * si + 1], &tr = tables[3 * si + 2];
+        std::vector<int32_t> &ta = tables[4 * si], &tb = tables[4 * si + 1], &tr = tables[4 * si + 2];
+        std::vector<int32_t> &tg = tables[4 * si + 3];
         size_t w_cursor = 0, p_cursor = 0;
         for (int gi : st.groups) {
             const Group &g = S.groups[gi];
             const Inst &I = inst[g.inst];
             double *W = I.mesh.cma ? nullptr : reinterpret_cast<double *>(ws + S.w_off + w_cursor);
             w_cursor += g.w_bytes;
-            const QDev qd = make_qdev(I.mesh, I.qs[g.q], W);
+            QDev qd = make_qdev(I.mesh, I.qs[g.q], W);
+            qd.rng_k = reinterpret_cast<double *>(ws + S.rng_off + g.rng_off);
+            qd.rng_kq = qd.rng_k + 2 * (size_t)I.mesh.nbw;
+            tg.push_back(g.items.front());
             for (size_t k = 0; k < g.items.size(); ++k) {
                 const int ii = g.items[k];
                 const Item &it = S.items[ii];
@@ -317,8 +337,8 @@ chi0_status install(chi0_batch_s *b, int64_t workgroups, int chunk, hipStream_t 
     hipError_t e = hipMemcpyAsync(b->ws + b->sched.items_off, b->items.data(), sizeof(BatchItemDev) * b->items.size(),
                                   hipMemcpyHostToDevice, s);
     for (size_t si = 0; e == hipSuccess && si < b->sched.stages.size(); ++si)
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-            const std::vector<int32_t> &t = b->tables[3 * si + k];
+        for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+            const std::vector<int32_t> &t = b->tables[4 * si + k];
             if (!t.empty())
                 e = hipMemcpyAsync(b->ws + b->sched.stages[si].table_off[k], t.data(), sizeof(int32_t) * t.size(),
                                    hipMemcpyHostToDevice, s);
@@ -332,10 +352,11 @@ hipError_t enqueue(chi0_batch_s *b, hipStream_t s)
 {
     const BatchItemDev *items = reinterpret_cast<const BatchItemDev *>(b->ws + b->sched.items_off);
     for (const Stage &st : b->sched.stages) {
-        const int32_t *t[3];
-        for (int k = 0; k < 3; ++k) t[k] = reinterpret_cast<const int32_t *>(b->ws + st.table_off[k]);
+        const int32_t *t[4];
+        for (int k = 0; k < 4; ++k) t[k] = reinterpret_cast<const int32_t *>(b->ws + st.table_off[k]);
         hipError_t e;
         if (st.blocks[0] > 0 && (e = launch_contract_batch(items, t[0], (int)st.blocks[0], s)) != hipSuccess) return e;
+        if ((e = launch_band_range_batch(items, t[3], (int)st.blocks[3], st.max_nbw, s)) != hipSuccess) return e;
         if ((e = launch_tetra_batch(items, t[1], (int)st.blocks[1], s)) != hipSuccess) return e;
         if ((e = launch_reduce_batch(items, t[2], (int)st.blocks[2], s)) != hipSuccess) return e;
     }

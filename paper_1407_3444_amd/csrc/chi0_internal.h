@@ -78,6 +78,11 @@ hipError_t launch_tetra_batch(const BatchItemDev *items, const int32_t *block_it
                               hipStream_t s);
 hipError_t launch_reduce_batch(const BatchItemDev *items, const int32_t *block_item, int nblocks_total,
                                hipStream_t s);
+// Band ranges of a batch stage: group_item[g] is the first item of (instance, q) group g, whose
+// QDev range pointers (shared by the group's items) receive e(k) and e(k+q); max_nbw bounds the
+// groups' band windows.
+hipError_t launch_band_range_batch(const BatchItemDev *items, const int32_t *group_item, int ngroups, int max_nbw,
+                                   hipStream_t s);
 
 // K_A: W_nm(k) = |sum_o conj(c_{o,n}(k)) c_{o,m}(k+q)|^2 for nq q-points of a batch.
 // precision 0: FP64 MFMA; 1: BF16 hi+lo split MFMA; 2: FP16 hi+lo split MFMA (FP32 accumulate).

@@ -181,12 +181,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ce
 // (b, 0) reduces band b of e(k) into rng_k, workgroup (b, 1 + i) band b of q i's e(k+q) into its
 // rng_kq (a mesh shift reads the plan's own energies).  NaN values are passed over.
 constexpr int kRangeThreads = 256;
-__global__ __launch_bounds__(kRangeThreads) void band_range_kernel(MeshDev M, BatchDev B)
+
+// out[0..1] = (min, max) of e[0..nk) by one workgroup of kRangeThreads.
+__device__ __forceinline__ void band_range_one(const double *__restrict__ e, int64_t nk, double *out)
 {
-    const int b = blockIdx.x, src = blockIdx.y;
-    const double *e = (src == 0 ? M.eps_k : B.q[src - 1].eps_kq) + (int64_t)(M.lo + b) * M.nk;
     double lo = INFINITY, hi = -INFINITY;
-    for (int64_t k = threadIdx.x; k < M.nk; k += kRangeThreads) {
+    for (int64_t k = threadIdx.x; k < nk; k += kRangeThreads) {
         const double v = e[k];
         lo = fmin(lo, v);
         hi = fmax(hi, v);
@@ -205,10 +205,27 @@ __global__ __launch_bounds__(kRangeThreads) void band_range_kernel(MeshDev M, Ba
             lo = fmin(lo, slo[i]);
             hi = fmax(hi, shi[i]);
         }
-        double *out = src == 0 ? B.q[0].rng_k : B.q[src - 1].rng_kq;
-        out[2 * b] = lo;
-        out[2 * b + 1] = hi;
+        out[0] = lo;
+        out[1] = hi;
     }
+}
+
+__global__ __launch_bounds__(kRangeThreads) void band_range_kernel(MeshDev M, BatchDev B)
+{
+    const int b = blockIdx.x, src = blockIdx.y;
+    const double *e = (src == 0 ? M.eps_k : B.q[src - 1].eps_kq) + (int64_t)(M.lo + b) * M.nk;
+    band_range_one(e, M.nk, (src == 0 ? B.q[0].rng_k : B.q[src - 1].rng_kq) + 2 * b);
+}
+
+// Batched form: workgroup (2 g + src, b) takes band b of group g's e(k) (src 0) or e(k+q) (src 1).
+__global__ __launch_bounds__(kRangeThreads) void band_range_batch_kernel(const BatchItemDev *__restrict__ items,
+                                                                         const int32_t *__restrict__ group_item)
+{
+    const int b = blockIdx.y, src = blockIdx.x & 1;
+    const BatchItemDev &it = items[group_item[blockIdx.x >> 1]];
+    if (b >= it.M.nbw) return;           // the whole workgroup: before any barrier
+    const double *e = (src == 0 ? it.M.eps_k : it.Q.eps_kq) + (int64_t)(it.M.lo + b) * it.M.nk;
+    band_range_one(e, it.M.nk, (src == 0 ? it.Q.rng_k : it.Q.rng_kq) + 2 * b);
 }
 
 }  // namespace
@@ -218,6 +235,15 @@ hipError_t launch_band_range(const MeshDev &mesh, const BatchDev &batch, int nq,
     if (!batch.q[0].rng_k) return hipSuccess;
     if (nq < 1 || nq > kMaxQBatch || mesh.nbw < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(band_range_kernel, dim3(mesh.nbw, nq + 1), dim3(kRangeThreads), 0, s, mesh, batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_range_batch(const BatchItemDev *items, const int32_t *group_item, int ngroups, int max_nbw,
+                                   hipStream_t s)
+{
+    if (ngroups < 1 || max_nbw < 1 || max_nbw > 65535 || ngroups > (1 << 30)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(band_range_batch_kernel, dim3(2 * ngroups, max_nbw), dim3(kRangeThreads), 0, s, items,
+                       group_item);
     return hipGetLastError();
 }
 
