@@ -83,8 +83,8 @@ VALUE_FORM = "FP64 path; the mixed forms, their speed-up over it and their error
 # HBM bytes per launch of the tetrahedron kernel on the default workload (16 q per launch), from
 # rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from a plain 1 GiB copy), valid for
 # the kernel sources with this hash only (see the counter summary under profiles/).
-TRAFFIC_KERNEL_SHA = "5ce64cf9ee8a9a26"
-TRAFFIC_BYTES_PER_LAUNCH = (337187.0 * 2.0 + 155647.7 * 1.0) * 1024
+TRAFFIC_KERNEL_SHA = "c97c6df10c9b3c23"
+TRAFFIC_BYTES_PER_LAUNCH = (337496.9 * 2.0 + 155647.3 * 1.0) * 1024
 
 
 def census_flops(census: dict, mixed: bool = False) -> int:

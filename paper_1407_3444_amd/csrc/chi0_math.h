@@ -657,9 +657,10 @@ C0_HD RD im_entry_poly(const double *v, const double *w)
     return r;
 }
 
-// entry over nodes i..i+P from its children B = [i..i+P-1], A = [i+1..i+P]
+// entry over nodes i..i+P from its children B = [i..i+P-1], A = [i+1..i+P]; inv = 1/(y[P] - y[0])
+// (read only when the nodes straddle w, so a span of zero never enters)
 template <int P>
-C0_HD RD im_entry(const double *y, const double *v, const double *w, RD A, RD B)
+C0_HD RD im_entry(const double *v, const double *w, RD A, RD B, double inv)
 {
     RD r;
     if (v[P] <= 0.0) {                 // every node at or below w: Im h vanishes on all of them
@@ -668,14 +669,27 @@ C0_HD RD im_entry(const double *y, const double *v, const double *w, RD A, RD B)
     } else if (v[0] >= 0.0) {          // every node at or above w: the plain cubic
         r = im_entry_poly<P>(v, w);
     } else {                           // nodes on both sides of w
-        const double inv = rcp(y[P] - y[0]);
         r.v = (A.v - B.v) * inv;
         r.t = fma(-r.v, (w[P] - w[0]) * inv, (A.t - B.t) * inv);
     }
     return r;
 }
 
-C0_HD double near_im(const double y[4], const double w[4], double om)
+// Reciprocals of the node spans of sorted nodes y that the straddling entries divide by, which
+// depend on the tetrahedron only: pairs (0,1), (1,2), (2,3), triples (0,2), (1,3), all (0,3).
+C0_HD void im_span_rcp(const double y[4], double inv[6])
+{
+    inv[0] = rcp(y[1] - y[0]);
+    inv[1] = rcp(y[2] - y[1]);
+    inv[2] = rcp(y[3] - y[2]);
+    inv[3] = rcp(y[2] - y[0]);
+    inv[4] = rcp(y[3] - y[1]);
+    inv[5] = rcp(y[3] - y[0]);
+}
+
+// Im sum_j W_j J_j for sorted nodes y with weights w at frequency om, given the span reciprocals
+// of im_span_rcp (computed once per tetrahedron by callers that evaluate many frequencies).
+C0_HD double near_im_spans(const double y[4], const double w[4], const double inv[6], double om)
 {
     double v[4];
 #pragma unroll
@@ -684,15 +698,22 @@ C0_HD double near_im(const double y[4], const double w[4], double om)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const RD z = {0.0, 0.0};
-        L0[i] = im_entry<0>(y + i, v + i, w + i, z, z);
+        L0[i] = im_entry<0>(v + i, w + i, z, z, 0.0);
     }
     RD L1[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) L1[i] = im_entry<1>(y + i, v + i, w + i, L0[i + 1], L0[i]);
+    for (int i = 0; i < 3; ++i) L1[i] = im_entry<1>(v + i, w + i, L0[i + 1], L0[i], inv[i]);
     RD L2[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) L2[i] = im_entry<2>(y + i, v + i, w + i, L1[i + 1], L1[i]);
-    return im_entry<3>(y, v, w, L2[1], L2[0]).t;
+    for (int i = 0; i < 2; ++i) L2[i] = im_entry<2>(v + i, w + i, L1[i + 1], L1[i], inv[3 + i]);
+    return im_entry<3>(v, w, L2[1], L2[0], inv[5]).t;
+}
+
+C0_HD double near_im(const double y[4], const double w[4], double om)
+{
+    double inv[6];
+    im_span_rcp(y, inv);
+    return near_im_spans(y, w, inv, om);
 }
 
 // Mixed form: a final tetrahedron whose sorted corner values have two neighbours closer than

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void te
 struct ImRec {
     double y[4];                // D at the corners (sorted ascending after the prep pass)
     double w[4];                // sign * volume * W
+    double inv[6];              // reciprocals of the node spans (prep pass, im_span_rcp)
 };
 constexpr int kCapIm = 64;      // final tetrahedra per LDS list
 static_assert(kCapIm >= kMaxRecsPerUnit, "a list must hold a whole unit");
@@ -41,12 +42,16 @@ __device__ __forceinline__ void drain_im(const ImRec *list, uint16_t (*queue)[kW
             --qn;
             const int e = queue[qn][lane];
             const int r = e >> 5, s = e & 31;
-            double y[4], w[4];
+            double y[4], w[4], inv[6];
 #pragma unroll
             for (int k = 0; k < 4; ++k) { y[k] = list[r].y[k]; w[k] = list[r].w[k]; }
-            const double v = near_im(y, w, omega[lane + kWave * s]);
 #pragma unroll
-            for (int ss = 0; ss < NSLOT; ++ss) acc[ss] += (s == ss) ? v : 0.0;
+            for (int k = 0; k < 6; ++k) inv[k] = list[r].inv[k];
+            const double v = near_im_spans(y, w, inv, omega[lane + kWave * s]);
+            // into the accumulator of slot s: an FMA with a factor 1 or 0 per slot (exactly acc + v or
+            // acc; only frequencies strictly inside a tetrahedron's range are queued, so v is finite)
+#pragma unroll
+            for (int ss = 0; ss < NSLOT; ++ss) acc[ss] = fma(s == ss ? 1.0 : 0.0, v, acc[ss]);
         }
     }
 }
@@ -101,8 +106,12 @@ __global__ __launch_bounds__(64) void tetra_im_kernel(MeshDev M, BatchDev B, int
                 double y[4] = {list[r].y[0], list[r].y[1], list[r].y[2], list[r].y[3]};
                 double w[4] = {list[r].w[0], list[r].w[1], list[r].w[2], list[r].w[3]};
                 sort4(y, w);
+                double inv[6];
+                im_span_rcp(y, inv);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { list[r].y[k] = y[k]; list[r].w[k] = w[k]; }
+#pragma unroll
+                for (int k = 0; k < 6; ++k) list[r].inv[k] = inv[k];
             }
             __syncthreads();
             for (int r = 0; r < nrec; ++r) {
