@@ -162,3 +162,32 @@ def test_batch_tune_keeps_results(batch_setup):
     for i, ins in enumerate(insts):
         ref = _single(ins)
         assert _relerr(tuned[i], ref) <= 1e-13, i
+
+
+def test_graph_replay_follows_band_energies_changed_in_place():
+    """The batched K_B skips band pairs whose energy ranges rule out a carved region; the ranges
+    are taken inside the captured launch sequence, so a replay after the band energies changed in
+    place must see the new ranges: a band moved from below the Fermi level to across it adds its
+    pairs' contributions, equal to a fresh single-plan call on the changed data."""
+    torch = _torch()
+    import paper_1407_3444_amd as lib
+    m = synth.random_model("tetragonal", 511, 6)
+    wl = synth.model_workload(m, (6, 6, 4), None, synth.omega_grid(96), shifts=[(1, 2, 1), (3, 0, 2)])
+    below = [b for b in range(wl.eps_k.shape[0]) if wl.eps_k[b].max() < wl.mu]
+    assert below, "the model needs a band entirely below the Fermi level"
+    ins = _instance(wl)
+    g = lib.Chi0Batch([ins], workgroups=256, use_graph=True)
+    first = g.run()[0].cpu().numpy().copy()
+    torch.cuda.synchronize()
+    assert _relerr(first, _single(ins)) <= 1e-13
+    b = below[0]
+    shift = float(wl.mu - wl.eps_k[b].mean())
+    _say("band", b, "moved by", shift, "eV across the Fermi level")
+    ins.eps_k[b] += shift                        # in place: the captured graph reads the same memory
+    torch.cuda.synchronize()
+    again = g.run()[0].cpu().numpy().copy()
+    torch.cuda.synchronize()
+    ref = _single(ins)
+    assert _relerr(again, ref) <= 1e-13
+    assert _relerr(again, first) > 1e-6          # the band's new pairs contribute
+    g.close()

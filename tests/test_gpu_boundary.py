@@ -216,3 +216,30 @@ def test_empty_q_list_and_frequency_grid_are_rejected_at_every_entry_point():
     got = plan.dynamic(qs, om).cpu().numpy()
     plan.sync()
     assert np.array_equal(got, ref)
+
+
+def test_plan_follows_band_energies_changed_in_place():
+    """A plan borrows its band energies; the band ranges from which the tetrahedron kernels skip
+    inert band pairs are taken anew by every call, so a band moved across the Fermi level in place
+    between two calls contributes in the second, which matches the oracle on the changed data."""
+    lib, torch, wl, plan, qs, om, eps, ck = _setup(q_subset=(3, 5))
+    first = plan.dynamic(qs, om).cpu().numpy()
+    plan.sync()
+    below = [b for b in range(wl.eps_k.shape[0]) if wl.eps_k[b].max() < wl.mu]
+    assert below, "the model needs a band entirely below the Fermi level"
+    b = below[-1]
+    shift = float(wl.mu - wl.eps_k[b].mean())
+    _say("band", b, "moved by", shift)
+    eps[b] += shift
+    wl.eps_k[b] += shift
+    for q in wl.qs:                      # explicit k+q energies of the same bands move alike
+        q.eps_kq[b] += shift
+    qs2 = [lib.Q(eps_kq=torch.from_numpy(q.eps_kq).to(eps.device), c_kq=q2.c_kq) for q, q2 in zip(wl.qs, qs)]
+    got = plan.dynamic(qs2, om).cpu().numpy()
+    plan.sync()
+    for j in range(len(qs2)):
+        ref = oracle.chi0(wl, j)
+        e = max_err(got[j], ref)
+        _say("q", j, "after the move: err", e)
+        assert e <= 1e-10
+    assert max_err(got[0], first[0]) > 1e-6
