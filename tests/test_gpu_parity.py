@@ -511,6 +511,28 @@ def test_dynamic_pairs_match_oracle_and_the_pair_sum(precision, nw):
     assert np.max(np.abs(got.sum(axis=(0, 1)) - total)) <= bound * np.max(np.abs(total))
 
 
+def test_full_size_dynamic_pairs_sampled():
+    """The pair-resolved dynamic call in the benchmark's configuration (10-orbital model, 64x64x8
+    mesh, 512 w, all 100 band pairs) on one q: three sampled frequencies of every pair against the
+    oracle's pair-resolved evaluation, per result against max(|ref|, 1e-3 of the largest |ref|);
+    the pair sum against chi0_dynamic at every frequency."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", q_subset=[21], workers=8)
+    plan, qs = _plan(wl)
+    om = torch.from_numpy(wl.omega).cuda()
+    _say("full-size dynamic pairs 64x64x8, 1 q x 512 w")
+    got = plan.dynamic_pairs(qs, om).cpu().numpy()[0]            # [nbw][nbw][nw]
+    sample = [17, 256, 490]
+    ref = oracle.chi0_pairs(wl, 0, omega=wl.omega[sample])
+    g = got[:, :, sample]
+    scale = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+    err = np.max(np.abs(g - ref) / scale)
+    _say(f"per-pair per-result error {err:.2e}")
+    assert err <= TOL
+    total = plan.dynamic(qs, om).cpu().numpy()[0]
+    assert np.max(np.abs(got.sum(axis=(0, 1)) - total)) <= 1e-13 * np.max(np.abs(total))
+
+
 def test_dynamic_pairs_rejects_list_plans():
     torch = _torch()
     import paper_1407_3444_amd as lib
