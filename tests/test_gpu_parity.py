@@ -239,6 +239,22 @@ def test_dynamic_mixed_precision_error(precision):
         assert err <= 1e-5
 
 
+@pytest.mark.parametrize("precision", [1, 2])
+def test_full_size_mixed_precision_sampled(precision):
+    """The mixed forms in the benchmark's configuration (64x64x8 mesh, 512 w, 16-q launch) on one
+    q: four sampled frequencies against the FP64 oracle, per result <= 1e-5."""
+    torch = _torch()
+    wl = synth.make_workload("tetra_dynamic", q_subset=[52], workers=8)
+    plan, qs = _plan(wl, precision=precision)
+    _say("full-size dynamic mixed precision", precision)
+    got = plan.dynamic(qs, torch.from_numpy(wl.omega).cuda()).cpu().numpy()[0]
+    sample = [3, 150, 301, 499]
+    ref = oracle.chi0(wl, 0, omega=wl.omega[sample])
+    err = _relerr(got[sample], ref)
+    _say(f"per-result error {err:.2e}")
+    assert err <= 1e-5
+
+
 def test_dynamic_mixed_precision_degenerate_model():
     """Mixed form on the single-band cubic model (CMA, explicit k+q): its symmetric mesh makes many
     final tetrahedra with tied or nearly tied corner values, which take the FP64 fallback of the
