@@ -426,6 +426,25 @@ def test_plane_wave_packed_operands(precision, n_pw, nb):
         assert abs(got - ref) <= 1e-5 * abs(ref), (i, got, ref)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_plane_wave_static(precision):
+    """The plane-wave configuration at full size (12^3 mesh, 4096 plane waves, 32 bands, 16 q by
+    mesh shift in one launch; the split form reads packed operands): static chi0 of two of the
+    q against the oracle, within the FP64 bar (FP64) or the mixed-form bar (BF16x3)."""
+    torch = _torch()
+    wl = synth.plane_wave_workload((12, 12, 12), 4096, 32, 16, 1, seed=11)
+    wl.static = True
+    plan, qs = _plan(wl, precision=precision)
+    _say("full-size plane-wave static, precision", precision)
+    got = plan.static(qs).cpu().numpy()
+    plan.sync()
+    for i in (0, 13):
+        ref = oracle.chi0(wl, i, omega=np.zeros(1))[0].real
+        err = abs(got[i] - ref) / abs(ref)
+        _say(f"q {i}: rel err {err:.2e}")
+        assert err <= (TOL if precision == 0 else 1e-5), (i, got[i], ref)
+
+
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_plane_wave_dynamic_chi0(precision):
     """chi0 with plane-wave matrix elements (300 plane waves, 6 bands) against the oracle: FP64
