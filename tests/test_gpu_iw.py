@@ -82,6 +82,25 @@ def test_wedge_point_group_loop_matches_oracle(kind, n):
     torch.cuda.synchronize()
 
 
+def test_full_size_wedge_sampled():
+    """The wedge configuration at full size (48^3 mesh: 13,824 tetrahedra, 6-orbital O_h model, all
+    48 group elements, 256 frequencies in the group call) on one q: six sampled frequencies against
+    the oracle's point-group loop, per result within the FP64 bar."""
+    torch = _torch()
+    q = np.array([0.23, 0.0, 0.0])
+    model = synth.cubic_s_model(5, 6)
+    kf, tets, vol, e, c, ents = _wedge_inputs(model, 48, q, False)
+    omega = synth.omega_grid(256)
+    plan, qs = _plan_and_qs(tets, vol, e, c, ents, mu=0.0)
+    _say("full-size wedge 48^3, 48 elements, 256 w")
+    got = plan.dynamic_group(qs, 48, _dev(omega)).cpu().numpy()[0]
+    sample = [0, 51, 102, 153, 204, 255]
+    ref = oracle.chi0_iw(e, c, ents, tets, vol, omega[sample], mu=0.0)
+    err = max_err(got[sample], ref)
+    _say("per-result error", err)
+    assert err <= TOL
+
+
 def test_group_packing_and_accumulation():
     """Groups of 3 (five per launch) and of 40 (three launches each, added in the reduction) equal
     the sums of the single-entry results."""
